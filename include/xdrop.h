@@ -1,0 +1,216 @@
+/*
+ * xdrop.h -- C ABI of the MI355X (gfx950) batched X-Drop seed-extension
+ * library.
+ *
+ * Operation (paper, Sec. 2.2 recurrence and X-Drop rule; Sec. 3 and
+ * Algorithm 1, memory-restricted antidiagonal sweep; Sec. 4.1.1 seed records
+ * and left/right extension split):
+ *
+ *   For each seed (q, t, q_pos, t_pos, k) two extensions are run:
+ *     left  over the reversed prefixes  q[0:q_pos]      and t[0:t_pos],
+ *     right over the suffixes           q[q_pos+k:]     and t[t_pos+k:].
+ *   An extension E(a, b) fills cells (x, y) by antidiagonals d = x + y,
+ *     S(0,0) = 0,
+ *     S(x,y) = max{ S(x-1,y-1) + sim(a[x-1], b[y-1]), S(x-1,y) + gap,
+ *                   S(x,y-1) + gap }   over predecessors inside the matrix,
+ *   and sets a cell to -infinity when it is below T - X, where T is the best
+ *   score of all earlier antidiagonals (strict '<').  The band of each
+ *   antidiagonal is the span reachable from the finite cells of the two
+ *   previous antidiagonals; the sweep stops when both hold no finite cell.
+ *   Result: best score T, the first cell reaching it (antidiagonal order,
+ *   lowest query offset on ties), and the live-span cell count.
+ *   score = left + seed_score + right, seed_score = sum of sim over the seed.
+ *
+ * All arithmetic is int32 and integer-only; results are bit-exact and do not
+ * depend on batch composition, order, variant, tile width or chunk size.
+ *
+ * Ownership: the caller owns every buffer passed in; the library keeps no
+ * pointer after the enqueued work completes.  A context owns its device
+ * workspace.  Threading: one host thread per context at a time.
+ * Errors: every function returns an xdrop_status; argument errors are
+ * detected on the host before any launch and leave outputs untouched;
+ * data-dependent errors (seed out of range, symbol outside the alphabet,
+ * score range, band cap) are reported per seed in xdrop_result.status while
+ * the other seeds are still computed.
+ */
+#ifndef XDROP_H
+#define XDROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XDROP_OK = 0,
+    XDROP_E_INVALID = -1,  /* bad argument (host-detected, nothing launched) */
+    XDROP_E_RANGE = -2,    /* per seed: seed outside its sequences, or the
+                              int32 score range could be exceeded */
+    XDROP_E_NOMEM = -3,    /* device or host allocation failed */
+    XDROP_E_DEVICE = -4,   /* HIP runtime error; sticky on the context */
+    XDROP_E_BUDGET = -5,   /* serving: request can never fit the budget */
+    XDROP_E_SYMBOL = -6,   /* per seed: a code >= alphabet_size */
+    XDROP_BAND_OVERFLOW = -7, /* per seed: band wider than opts->band_cap */
+    XDROP_PENDING = 1      /* serving: request not finished yet */
+} xdrop_status;
+
+/* Sequence encodings. */
+enum {
+    XDROP_DNA2 = 0, /* 2 bits per code, 16 codes per little-endian 32-bit
+                       word, code i of the stream at bits 2*(i%16) of word
+                       i/16; A=0 C=1 G=2 T=3 */
+    XDROP_BYTE = 1  /* one code per byte, code < alphabet_size (<= 32) */
+};
+
+/* Scoring scheme (host struct, copied at the call). */
+typedef struct {
+    int32_t alphabet;      /* XDROP_DNA2 or XDROP_BYTE */
+    int32_t alphabet_size; /* 4 for XDROP_DNA2; 1..32 for XDROP_BYTE */
+    int32_t match;         /* used iff matrix == NULL */
+    int32_t mismatch;      /* used iff matrix == NULL */
+    const int32_t *matrix; /* host, alphabet_size^2, row = query code,
+                              column = target code; |entry| <= 1024 */
+    int32_t gap;           /* linear gap, added per gap symbol; -1024..0 */
+    int32_t X;             /* X-Drop threshold, >= 0 (INT32_MAX allowed) */
+} xdrop_scoring;
+
+/* Seed record (device array, 20 bytes each). The seed aligns q[q_pos, q_pos+k)
+ * against t[t_pos, t_pos+k); q and t index the offsets table. */
+typedef struct {
+    int32_t q, t;
+    int32_t q_pos, t_pos, k;
+} xdrop_seed;
+
+/* Per-seed result (device array, 48 bytes each). Positions are half-open
+ * intervals on q and t after extension. */
+typedef struct {
+    int32_t score, left, right, seed_score;
+    int32_t q_begin, q_end, t_begin, t_end;
+    int64_t cells;  /* live-span cells of both extensions */
+    int32_t status; /* XDROP_OK or a per-seed error */
+    int32_t reserved;
+} xdrop_result;
+
+/* Launch options (host struct; NULL = defaults). */
+enum {
+    XDROP_VARIANT_AUTO = 0,      /* choose per batch (tuned table or default) */
+    XDROP_VARIANT_WAVE = 1,      /* one wavefront per extension */
+    XDROP_VARIANT_WORKGROUP = 2, /* one 4-wave workgroup per extension */
+    XDROP_VARIANT_PLAIN = 3      /* one wave per extension, one launch wave per
+                                    extension, no queue: the baseline form */
+};
+typedef struct {
+    int32_t variant;      /* XDROP_VARIANT_* */
+    int32_t tile;         /* starting cells per lane: 1, 2, 4, 8 or 16
+                             (band tile 64..1024); 0 = automatic */
+    int32_t chunk;        /* extensions claimed per queue access, 1..64;
+                             0 = automatic */
+    int32_t band_cap;     /* > 0: seeds whose band exceeds it get
+                             XDROP_BAND_OVERFLOW; 0 = no cap */
+    int32_t order;        /* 0: longest-first (by m+n) queue order;
+                             1: input order */
+    int32_t waves_per_cu; /* persistent grid size; 0 = automatic */
+    int32_t reserved[2];
+} xdrop_options;
+
+typedef struct xdrop_ctx xdrop_ctx;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int xdrop_ctx_create(int device, xdrop_ctx **out);
+int xdrop_ctx_destroy(xdrop_ctx *ctx);
+
+/* Extend every seed of a batch.
+ *   d_seqs    device, packed sequence stream (encoding = scoring->alphabet);
+ *             readable up to the next multiple of 16 bytes past its end
+ *   d_offsets device, n_seqs+1 int64 symbol offsets; sequence s is symbols
+ *             [d_offsets[s], d_offsets[s+1]) of the stream (no alignment
+ *             requirement)
+ *   d_seeds   device, n_seeds records
+ *   d_results device, n_seeds records, written by the enqueued work
+ *   stream    hipStream_t (as void*), NULL = default stream
+ * Enqueues the work and returns; results are valid after the stream
+ * synchronises.  Inputs must stay alive until then.  n_seeds == 0 is a no-op.
+ * Returns XDROP_E_INVALID on bad arguments (nothing is launched),
+ * XDROP_E_NOMEM / XDROP_E_DEVICE on runtime failures. */
+int xdrop_extend_batch(xdrop_ctx *ctx, const uint8_t *d_seqs,
+                       const int64_t *d_offsets, int32_t n_seqs,
+                       const xdrop_seed *d_seeds, int32_t n_seeds,
+                       const xdrop_scoring *scoring,
+                       const xdrop_options *opts, xdrop_result *d_results,
+                       void *stream);
+
+/* Autotune the launch parameters on a sample batch (same arguments as
+ * xdrop_extend_batch; d_results is scratch) by timing every candidate
+ * variant / tile / chunk on `stream`; the best is stored in the context for
+ * batches of this alphabet and, if cache_path is not NULL, appended to that
+ * JSON-lines file.  *best_out (optional) receives the chosen options. */
+int xdrop_autotune(xdrop_ctx *ctx, const uint8_t *d_seqs,
+                   const int64_t *d_offsets, int32_t n_seqs,
+                   const xdrop_seed *d_seeds, int32_t n_seeds,
+                   const xdrop_scoring *scoring, xdrop_result *d_results,
+                   void *stream, const char *cache_path,
+                   xdrop_options *best_out);
+
+/* Load tuned options from a JSON-lines cache written by xdrop_autotune. */
+int xdrop_load_tuning(xdrop_ctx *ctx, const char *cache_path);
+
+/* Capture the launch sequence of one batch shape into a HIP graph and replay
+ * it: identical to xdrop_extend_batch, but the launches are recorded once per
+ * (pointers, sizes, scoring, options) and replayed afterwards. */
+int xdrop_extend_batch_graph(xdrop_ctx *ctx, const uint8_t *d_seqs,
+                             const int64_t *d_offsets, int32_t n_seqs,
+                             const xdrop_seed *d_seeds, int32_t n_seeds,
+                             const xdrop_scoring *scoring,
+                             const xdrop_options *opts,
+                             xdrop_result *d_results, void *stream);
+
+/* Statistics of the last batch on this context (after stream sync):
+ * counts of extensions finished at each tile width (1, 2, 4, 8, 16 cells per
+ * lane, workgroup tier, general tier). */
+int xdrop_last_stats(xdrop_ctx *ctx, int64_t *counts, int32_t n_counts);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching: requests (host sequences + seeds + scoring) are
+ * admitted against a device-memory budget, copied into a resident pool, and
+ * their extensions are fed to a device queue that the worker keeps draining;
+ * requests that arrive while others run are admitted as memory frees up.
+ */
+typedef struct xdrop_server xdrop_server;
+
+typedef struct {
+    const uint8_t *seqs;     /* host, packed stream as for xdrop_extend_batch */
+    const int64_t *offsets;  /* host, n_seqs+1 */
+    int32_t n_seqs;
+    const xdrop_seed *seeds; /* host */
+    int32_t n_seeds;
+    xdrop_scoring scoring;
+} xdrop_request;
+
+typedef struct {
+    int32_t max_inflight;   /* requests resident at once; 0 = 256 */
+    int32_t worker_waves;   /* device waves of the resident worker; 0 = auto */
+    int32_t reserved[6];
+} xdrop_server_opts;
+
+int xdrop_server_create(int device, size_t hbm_budget_bytes,
+                        const xdrop_server_opts *opts, xdrop_server **out);
+/* Copies the request; returns XDROP_E_BUDGET if it can never fit. */
+int xdrop_server_submit(xdrop_server *srv, const xdrop_request *req,
+                        uint64_t *ticket);
+/* XDROP_PENDING or XDROP_OK (then host_out holds n_seeds results and the
+ * ticket is released). */
+int xdrop_server_poll(xdrop_server *srv, uint64_t ticket,
+                      xdrop_result *host_out);
+/* Block until done or timeout_ns passes (< 0: no limit). */
+int xdrop_server_wait(xdrop_server *srv, uint64_t ticket,
+                      xdrop_result *host_out, int64_t timeout_ns);
+int xdrop_server_destroy(xdrop_server *srv);
+
+const char *xdrop_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XDROP_H */

@@ -77,7 +77,8 @@ def _load():
                                        ctypes.c_int64,
                                        ctypes.POINTER(_Scoring),
                                        ctypes.POINTER(_Ext),
-                                       ctypes.POINTER(ctypes.c_int32)]
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int64)]
         lib.xo_seed_extend.argtypes = [u8p, ctypes.c_int64, u8p,
                                        ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int64, ctypes.c_int64,
@@ -149,7 +150,7 @@ def extend(a, b, scoring: Scoring, tier: str = "dense"):
                                  ctypes.byref(out), None, None)
     elif tier == "span":
         rc = lib.xo_extend_span(pa, a.size, pb, b.size, ctypes.byref(sc),
-                                ctypes.byref(out), None)
+                                ctypes.byref(out), None, None)
     else:
         raise ValueError(tier)
     if rc != OK:
@@ -177,22 +178,25 @@ def extend_matrix(a, b, scoring: Scoring):
     return (int(out.best), int(out.x), int(out.y), int(out.cells)), S, F.astype(bool)
 
 
-def band_widths(a, b, scoring: Scoring) -> np.ndarray:
-    """Working band hi_d - lo_d + 1 per antidiagonal (Sec. 5.4 study)."""
+def band_widths(a, b, scoring: Scoring, finite: bool = False):
+    """Working band hi_d - lo_d + 1 per antidiagonal (Sec. 5.4 study); with
+    finite=True also the finite range (L_d, U_d; -1 when dead) per d."""
     lib = _load()
     a = _u8(a)
     b = _u8(b)
     sc, keep = scoring._c()
     out = _Ext()
     w = np.zeros(a.size + b.size + 1, dtype=np.int32)
+    fr = np.zeros((a.size + b.size + 1, 2), dtype=np.int64)
     pa, ka = _ptr(a)
     pb, kb = _ptr(b)
     rc = lib.xo_extend_span(pa, a.size, pb, b.size, ctypes.byref(sc),
                             ctypes.byref(out),
-                            w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+                            w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            fr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     if rc != OK:
         raise RuntimeError(f"oracle error {rc}")
-    return w
+    return (w, fr) if finite else w
 
 
 def seed_extend(q, t, q_pos: int, t_pos: int, k: int, scoring: Scoring,

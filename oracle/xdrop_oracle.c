@@ -239,9 +239,11 @@ static xo_cell xo_get(const xo_diag *D, const xo_cell *store, int64_t d,
 }
 
 /* widths (optional, m+n+1 entries): hi_d - lo_d + 1 per antidiagonal, 0 when
- * empty -- the working band of Sec. 5.4. */
+ * empty -- the working band of Sec. 5.4.  finite (optional, 2*(m+n+1)
+ * entries): L_d, U_d per antidiagonal, -1, -1 when it holds no finite cell. */
 int xo_extend_span(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
-                   const xo_scoring *sc, xo_ext *out, int32_t *widths)
+                   const xo_scoring *sc, xo_ext *out, int32_t *widths,
+                   int64_t *finite)
 {
     if (m < 0 || n < 0 || sc->X < 0)
         return XO_E_INVALID;
@@ -264,6 +266,11 @@ int xo_extend_span(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
         widths[0] = 1;
         for (int64_t d = 1; d < nd; d++)
             widths[d] = 0;
+    }
+    if (finite) {
+        finite[0] = finite[1] = 0;
+        for (int64_t d = 1; d < nd; d++)
+            finite[2 * d] = finite[2 * d + 1] = -1;
     }
 
     int64_t T = 0, bx = 0, by = 0, W = 1;
@@ -334,6 +341,10 @@ int xo_extend_span(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
             store[used + (size_t)(x - e->lo)] = s;
         }
         used += (size_t)len;
+        if (finite && e->alive) {
+            finite[2 * d] = e->L;
+            finite[2 * d + 1] = e->U;
+        }
         if (dmax_x >= 0 && dmax > T) {
             T = dmax;
             bx = dmax_x;
@@ -370,7 +381,7 @@ static int xo_run(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
 {
     if ((m + 1) * (n + 1) <= dense_limit)
         return xo_extend_dense(a, m, b, n, sc, e, NULL, NULL);
-    return xo_extend_span(a, m, b, n, sc, e, NULL);
+    return xo_extend_span(a, m, b, n, sc, e, NULL, NULL);
 }
 
 int xo_seed_extend(const uint8_t *q, int64_t qlen, const uint8_t *t,

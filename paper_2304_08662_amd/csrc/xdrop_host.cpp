@@ -1,0 +1,591 @@
+// Host side of the X-Drop library: argument checks, workspace, launch
+// sequence, autotuning and graph replay.  The C ABI is declared in
+// include/xdrop.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "xdrop.h"
+#include "xdrop_internal.h"
+
+using namespace xd;
+
+struct GraphEntry {
+  // launch inputs the captured graph is valid for
+  const void* seqs;
+  const void* offsets;
+  const void* seeds;
+  void* results;
+  int32_t n_seqs, n_seeds;
+  xdrop_scoring sc;
+  std::vector<int32_t> matrix;
+  xdrop_options opts;
+  hipStream_t stream;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct xdrop_ctx {
+  int device = 0;
+  int num_cu = 0;
+  int sticky = XDROP_OK;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t* counters = nullptr;
+  int32_t* gen_scratch = nullptr;
+  int gen_slots = 32;
+  int blocks_per_cu[2][2] = {{0, 0}, {0, 0}};  // [alphabet][wide]
+  bool have_tuned[2] = {false, false};
+  xdrop_options tuned[2];
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Layout {
+  size_t items, order, wide_q, gen_q, bad, total;
+};
+
+Layout layout(int32_t n_items, int32_t n_seqs) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes > 0 ? bytes : 1);
+    return o;
+  };
+  const size_t ni = (size_t)std::max(n_items, 1);
+  L.items = take(ni * sizeof(ItemResult));
+  L.order = take(ni * 4);
+  L.wide_q = take(ni * 4);
+  L.gen_q = take(ni * 4);
+  L.bad = take((size_t)std::max(n_seqs, 1));
+  L.total = off;
+  return L;
+}
+
+int fail(xdrop_ctx* c, hipError_t e) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return XDROP_E_NOMEM;
+  if (c) c->sticky = XDROP_E_DEVICE;
+  return XDROP_E_DEVICE;
+}
+
+#define HIP_OK(expr)                     \
+  do {                                   \
+    hipError_t e_ = (expr);              \
+    if (e_ != hipSuccess) return fail(c, e_); \
+  } while (0)
+
+// Scoring checks and the kernel-side constants.
+int fill_scoring(const xdrop_scoring* sc, Params& P) {
+  if (!sc) return XDROP_E_INVALID;
+  if (sc->alphabet != XDROP_DNA2 && sc->alphabet != XDROP_BYTE)
+    return XDROP_E_INVALID;
+  if (sc->gap > 0 || sc->gap < -MAX_ENTRY || sc->X < 0) return XDROP_E_INVALID;
+  const int A = sc->alphabet_size;
+  if (sc->alphabet == XDROP_DNA2 && A != 4) return XDROP_E_INVALID;
+  if (sc->alphabet == XDROP_BYTE && (A < 1 || A > TABLE_DIM))
+    return XDROP_E_INVALID;
+  std::vector<int32_t> M((size_t)A * A);
+  if (sc->matrix) {
+    for (int i = 0; i < A * A; ++i) M[i] = sc->matrix[i];
+  } else {
+    for (int i = 0; i < A; ++i)
+      for (int j = 0; j < A; ++j)
+        M[(size_t)i * A + j] = i == j ? sc->match : sc->mismatch;
+  }
+  int max_abs = 0;
+  for (int32_t v : M) {
+    if (v > MAX_ENTRY || v < -MAX_ENTRY) return XDROP_E_INVALID;
+    max_abs = std::max(max_abs, std::abs(v));
+  }
+  const int g = sc->gap;
+  P.alphabet = sc->alphabet;
+  P.gap = g;
+  P.X = std::min(sc->X, X_CLAMP);
+  P.max_abs = max_abs + 2 * std::abs(g);
+  if (P.max_abs == 0) P.max_abs = 1;
+  std::memset(P.table, 0, sizeof(P.table));
+  if (sc->alphabet == XDROP_DNA2) {
+    // the 2-bit path compares codes: the matrix must be match / mismatch
+    const int32_t mt = M[0], mm = M[1];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        if (M[i * 4 + j] != (i == j ? mt : mm)) return XDROP_E_INVALID;
+    P.mat_s = mt - 2 * g;
+    P.mis_s = mm - 2 * g;
+  } else {
+    P.mat_s = P.mis_s = 0;
+    for (int i = 0; i < A; ++i)
+      for (int j = 0; j < A; ++j)
+        P.table[i * TABLE_DIM + j] = (int16_t)(M[(size_t)i * A + j] - 2 * g);
+  }
+  return XDROP_OK;
+}
+
+int check_options(const xdrop_options* o) {
+  if (!o) return XDROP_OK;
+  if (o->variant < 0 || o->variant > XDROP_VARIANT_PLAIN) return XDROP_E_INVALID;
+  const int t = o->tile;
+  if (!(t == 0 || t == 1 || t == 2 || t == 4 || t == 8 || t == 16))
+    return XDROP_E_INVALID;
+  if (o->chunk < 0 || o->chunk > 64) return XDROP_E_INVALID;
+  if (o->band_cap < 0 || o->order < 0 || o->order > 1 ||
+      o->waves_per_cu < 0 || o->waves_per_cu > 64)
+    return XDROP_E_INVALID;
+  return XDROP_OK;
+}
+
+xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
+                      const xdrop_options* o) {
+  xdrop_options r{};
+  const int a = sc->alphabet == XDROP_BYTE ? 1 : 0;
+  if (c->have_tuned[a]) r = c->tuned[a];
+  if (o) {
+    if (o->variant) r.variant = o->variant;
+    if (o->tile) r.tile = o->tile;
+    if (o->chunk) r.chunk = o->chunk;
+    r.band_cap = o->band_cap;
+    r.order = o->order;
+    if (o->waves_per_cu) r.waves_per_cu = o->waves_per_cu;
+  }
+  if (!r.variant) r.variant = XDROP_VARIANT_WAVE;
+  if (!r.tile) r.tile = 1;
+  if (!r.chunk) r.chunk = 1;
+  return r;
+}
+
+int ensure_workspace(xdrop_ctx* c, size_t bytes) {
+  if (!c->counters) {
+    HIP_OK(hipMalloc(&c->counters, C_COUNT * sizeof(int32_t)));
+    HIP_OK(hipMemset(c->counters, 0, C_COUNT * sizeof(int32_t)));
+  }
+  if (!c->gen_scratch) {
+    HIP_OK(hipMalloc(&c->gen_scratch,
+                     (size_t)c->gen_slots * 3 * GEN_CAP * sizeof(int32_t)));
+  }
+  if (bytes > c->ws_bytes) {
+    if (c->ws) HIP_OK(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    size_t want = bytes + bytes / 4;
+    HIP_OK(hipMalloc(&c->ws, want));
+    c->ws_bytes = want;
+  }
+  return XDROP_OK;
+}
+
+// Enqueue the whole launch sequence of one batch on `st`.
+int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
+            int32_t n_seqs, const xdrop_seed* d_seeds, int32_t n_seeds,
+            const xdrop_scoring* sc, const xdrop_options* opts,
+            xdrop_result* d_results, hipStream_t st) {
+  Params P;
+  std::memset(&P, 0, sizeof(P));
+  int rc = fill_scoring(sc, P);
+  if (rc != XDROP_OK) return rc;
+  rc = check_options(opts);
+  if (rc != XDROP_OK) return rc;
+  if (n_seeds < 0 || n_seqs < 0 || n_seeds > (1 << 29)) return XDROP_E_INVALID;
+  if (n_seeds == 0) return XDROP_OK;
+  if (!d_seqs || !d_offsets || !d_seeds || !d_results || n_seqs == 0)
+    return XDROP_E_INVALID;
+  const xdrop_options o = resolve(c, sc, opts);
+  const int32_t n_items = 2 * n_seeds;
+  Layout L = layout(n_items, n_seqs);
+  rc = ensure_workspace(c, L.total);
+  if (rc != XDROP_OK) return rc;
+  char* ws = (char*)c->ws;
+
+  P.seqs = (const uint32_t*)d_seqs;
+  P.offsets = d_offsets;
+  P.seeds = (const int32_t*)d_seeds;
+  P.items = (ItemResult*)(ws + L.items);
+  P.counters = c->counters;
+  P.wide_queue = (int32_t*)(ws + L.wide_q);
+  P.gen_queue = (int32_t*)(ws + L.gen_q);
+  P.gen_scratch = c->gen_scratch;
+  P.n_seqs = n_seqs;
+  P.n_seeds = n_seeds;
+  P.n_items = n_items;
+  P.tile = o.tile;
+  P.chunk = o.chunk;
+  P.band_cap = o.band_cap;
+  P.gen_slots = c->gen_slots;
+  const bool plain = o.variant == XDROP_VARIANT_PLAIN;
+  P.flags = plain ? F_PLAIN : 0;
+
+  HIP_OK(launch_reset(c->counters, st));
+  if (P.alphabet == 1) {
+    P.seq_bad = (const uint8_t*)(ws + L.bad);
+    HIP_OK(launch_validate(d_seqs, d_offsets, n_seqs, sc->alphabet_size,
+                           (uint8_t*)(ws + L.bad),
+                           std::min(c->num_cu * 8, (n_seqs + 3) / 4 + 1), st));
+  }
+  if (o.order == 0 && !plain) {
+    int32_t* ord = (int32_t*)(ws + L.order);
+    HIP_OK(launch_order(P.seeds, d_offsets, n_seqs, n_items, c->counters, ord,
+                        c->num_cu, st));
+    P.order = ord;
+    P.flags |= F_ORDERED;
+  }
+  const int a = P.alphabet;
+  if (!c->blocks_per_cu[a][0]) {
+    c->blocks_per_cu[a][0] = wave_blocks_per_cu(a, 8);
+    c->blocks_per_cu[a][1] = wave_blocks_per_cu(a, 16);
+  }
+  auto persistent_grid = [&](int wide) {
+    int bpc = c->blocks_per_cu[a][wide];
+    if (o.waves_per_cu > 0)
+      bpc = std::max(1, std::min(bpc, (o.waves_per_cu + WPB - 1) / WPB));
+    return c->num_cu * bpc;
+  };
+  if (o.variant == XDROP_VARIANT_WORKGROUP) {
+    // every extension on the workgroup tier
+    HIP_OK(launch_fill_queue(P.order, n_items, P.gen_queue, c->counters,
+                             C_GEN_TAIL, st));
+  } else {
+    int grid;
+    if (plain)
+      grid = (n_items + WPB - 1) / WPB;
+    else
+      grid = std::min(persistent_grid(0),
+                      (n_items + WPB * o.chunk - 1) / (WPB * o.chunk));
+    HIP_OK(launch_wave(P, 8, grid, st));
+    HIP_OK(launch_wave(P, 16, std::min(persistent_grid(1),
+                                       (n_items + WPB - 1) / WPB), st));
+  }
+  HIP_OK(launch_general(P, c->gen_slots, st));
+  HIP_OK(launch_combine(P, d_results, st));
+  return XDROP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xdrop_strerror(int s) {
+  switch (s) {
+    case XDROP_OK: return "ok";
+    case XDROP_E_INVALID: return "invalid argument";
+    case XDROP_E_RANGE: return "seed or score out of range";
+    case XDROP_E_NOMEM: return "out of memory";
+    case XDROP_E_DEVICE: return "device error";
+    case XDROP_E_BUDGET: return "request exceeds the memory budget";
+    case XDROP_E_SYMBOL: return "symbol outside the alphabet";
+    case XDROP_BAND_OVERFLOW: return "band wider than the cap";
+    case XDROP_PENDING: return "pending";
+    default: return "unknown status";
+  }
+}
+
+int xdrop_ctx_create(int device, xdrop_ctx** out) {
+  if (!out) return XDROP_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return XDROP_E_INVALID;
+  xdrop_ctx* c = new (std::nothrow) xdrop_ctx();
+  if (!c) return XDROP_E_NOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return XDROP_E_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return XDROP_E_DEVICE;
+  }
+  c->num_cu = prop.multiProcessorCount;
+  *out = c;
+  return XDROP_OK;
+}
+
+int xdrop_ctx_destroy(xdrop_ctx* c) {
+  if (!c) return XDROP_E_INVALID;
+  (void)hipSetDevice(c->device);
+  for (auto& g : c->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->counters) (void)hipFree(c->counters);
+  if (c->gen_scratch) (void)hipFree(c->gen_scratch);
+  delete c;
+  return XDROP_OK;
+}
+
+int xdrop_extend_batch(xdrop_ctx* c, const uint8_t* d_seqs,
+                       const int64_t* d_offsets, int32_t n_seqs,
+                       const xdrop_seed* d_seeds, int32_t n_seeds,
+                       const xdrop_scoring* scoring, const xdrop_options* opts,
+                       xdrop_result* d_results, void* stream) {
+  if (!c) return XDROP_E_INVALID;
+  if (c->sticky != XDROP_OK) return c->sticky;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
+  return enqueue(c, d_seqs, d_offsets, n_seqs, d_seeds, n_seeds, scoring,
+                 opts, d_results, (hipStream_t)stream);
+}
+
+int xdrop_last_stats(xdrop_ctx* c, int64_t* counts, int32_t n_counts) {
+  if (!c || !counts || n_counts < 0) return XDROP_E_INVALID;
+  int32_t h[C_COUNT] = {0};
+  if (c->counters) {
+    if (hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return fail(c, hipErrorUnknown);
+  }
+  for (int i = 0; i < n_counts; ++i)
+    counts[i] = i < 6 ? h[C_TIER0 + i] : 0;
+  return XDROP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ graphs
+namespace {
+
+bool same_scoring(const GraphEntry& g, const xdrop_scoring* sc) {
+  if (g.sc.alphabet != sc->alphabet || g.sc.alphabet_size != sc->alphabet_size ||
+      g.sc.match != sc->match || g.sc.mismatch != sc->mismatch ||
+      g.sc.gap != sc->gap || g.sc.X != sc->X)
+    return false;
+  if ((sc->matrix == nullptr) != g.matrix.empty()) return false;
+  if (sc->matrix) {
+    const size_t n = (size_t)sc->alphabet_size * sc->alphabet_size;
+    if (g.matrix.size() != n) return false;
+    for (size_t i = 0; i < n; ++i)
+      if (g.matrix[i] != sc->matrix[i]) return false;
+  }
+  return true;
+}
+
+bool same_opts(const xdrop_options& a, const xdrop_options& b) {
+  return a.variant == b.variant && a.tile == b.tile && a.chunk == b.chunk &&
+         a.band_cap == b.band_cap && a.order == b.order &&
+         a.waves_per_cu == b.waves_per_cu;
+}
+
+void drop_graphs(xdrop_ctx* c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  c->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" int xdrop_extend_batch_graph(
+    xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
+    int32_t n_seqs, const xdrop_seed* d_seeds, int32_t n_seeds,
+    const xdrop_scoring* sc, const xdrop_options* opts,
+    xdrop_result* d_results, void* stream) {
+  if (!c) return XDROP_E_INVALID;
+  if (c->sticky != XDROP_OK) return c->sticky;
+  hipStream_t st = (hipStream_t)stream;
+  if (!st) return XDROP_E_INVALID;  // the legacy stream cannot be captured
+  Params tmp;
+  int rc = fill_scoring(sc, tmp);
+  if (rc != XDROP_OK) return rc;
+  rc = check_options(opts);
+  if (rc != XDROP_OK) return rc;
+  if (n_seeds < 0 || n_seqs < 0 || n_seeds > (1 << 29)) return XDROP_E_INVALID;
+  if (n_seeds == 0) return XDROP_OK;
+  if (!d_seqs || !d_offsets || !d_seeds || !d_results || n_seqs == 0)
+    return XDROP_E_INVALID;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
+  const xdrop_options o = resolve(c, sc, opts);
+  for (auto& g : c->graphs) {
+    if (g.seqs == d_seqs && g.offsets == d_offsets && g.seeds == d_seeds &&
+        g.results == d_results && g.n_seqs == n_seqs &&
+        g.n_seeds == n_seeds && g.stream == st && same_scoring(g, sc) &&
+        same_opts(g.opts, o)) {
+      HIP_OK(hipGraphLaunch(g.exec, st));
+      return XDROP_OK;
+    }
+  }
+  // everything that allocates or queries happens before the capture
+  Layout L = layout(2 * n_seeds, n_seqs);
+  if (L.total > c->ws_bytes) drop_graphs(c);  // the workspace moves
+  rc = ensure_workspace(c, L.total);
+  if (rc != XDROP_OK) return rc;
+  for (int a = 0; a < 2; ++a)
+    if (!c->blocks_per_cu[a][0]) {
+      c->blocks_per_cu[a][0] = wave_blocks_per_cu(a, 8);
+      c->blocks_per_cu[a][1] = wave_blocks_per_cu(a, 16);
+    }
+  GraphEntry g;
+  g.seqs = d_seqs; g.offsets = d_offsets; g.seeds = d_seeds;
+  g.results = d_results; g.n_seqs = n_seqs; g.n_seeds = n_seeds;
+  g.sc = *sc;
+  if (sc->matrix)
+    g.matrix.assign(sc->matrix,
+                    sc->matrix + (size_t)sc->alphabet_size * sc->alphabet_size);
+  g.sc.matrix = nullptr;
+  g.opts = o;
+  g.stream = st;
+  HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  rc = enqueue(c, d_seqs, d_offsets, n_seqs, d_seeds, n_seeds, sc, &o,
+               d_results, st);
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (rc != XDROP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ce != hipSuccess) return fail(c, ce);
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(c, ie);
+  }
+  g.graph = graph;
+  g.exec = exec;
+  c->graphs.push_back(std::move(g));
+  if (c->graphs.size() > 64) {  // bounded cache: drop the oldest
+    auto& old = c->graphs.front();
+    (void)hipGraphExecDestroy(old.exec);
+    (void)hipGraphDestroy(old.graph);
+    c->graphs.erase(c->graphs.begin());
+  }
+  HIP_OK(hipGraphLaunch(exec, st));
+  return XDROP_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
+                              const int64_t* d_offsets, int32_t n_seqs,
+                              const xdrop_seed* d_seeds, int32_t n_seeds,
+                              const xdrop_scoring* sc,
+                              xdrop_result* d_results, void* stream,
+                              const char* cache_path,
+                              xdrop_options* best_out) {
+  if (!c || !sc) return XDROP_E_INVALID;
+  if (c->sticky != XDROP_OK) return c->sticky;
+  if (n_seeds <= 0) return XDROP_E_INVALID;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
+  hipStream_t st = (hipStream_t)stream;
+  const int a = sc->alphabet == XDROP_BYTE ? 1 : 0;
+  // candidates: persistent wave form (tile x chunk), the plain form (tile),
+  // the workgroup form
+  std::vector<xdrop_options> cand;
+  const int tiles[] = {1, 2, 4, 8, 16};
+  const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
+  for (int t : tiles)
+    for (int ch : chunks) {
+      xdrop_options o{};
+      o.variant = XDROP_VARIANT_WAVE; o.tile = t; o.chunk = ch;
+      cand.push_back(o);
+    }
+  for (int t : tiles) {
+    xdrop_options o{};
+    o.variant = XDROP_VARIANT_PLAIN; o.tile = t; o.chunk = 1;
+    cand.push_back(o);
+  }
+  {
+    xdrop_options o{};
+    o.variant = XDROP_VARIANT_WORKGROUP; o.tile = 1; o.chunk = 1;
+    cand.push_back(o);
+  }
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  const bool saved = c->have_tuned[a];
+  c->have_tuned[a] = false;  // time each candidate as given
+  float best_ms = 1e30f;
+  xdrop_options best{};
+  int rc = XDROP_OK;
+  for (const auto& o : cand) {
+    // one warm run, then the median of three timed runs (one if slow)
+    rc = enqueue(c, d_seqs, d_offsets, n_seqs, d_seeds, n_seeds, sc, &o,
+                 d_results, st);
+    if (rc != XDROP_OK) break;
+    float t[3];
+    int reps = 3;
+    for (int r = 0; r < reps; ++r) {
+      HIP_OK(hipEventRecord(e0, st));
+      rc = enqueue(c, d_seqs, d_offsets, n_seqs, d_seeds, n_seeds, sc, &o,
+                   d_results, st);
+      if (rc != XDROP_OK) break;
+      HIP_OK(hipEventRecord(e1, st));
+      HIP_OK(hipEventSynchronize(e1));
+      HIP_OK(hipEventElapsedTime(&t[r], e0, e1));
+      if (r == 0 && t[0] > 3.0f * best_ms) { reps = 1; break; }
+    }
+    if (rc != XDROP_OK) break;
+    std::sort(t, t + reps);
+    const float ms = t[reps / 2];
+    if (ms < best_ms) { best_ms = ms; best = o; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != XDROP_OK) {
+    c->have_tuned[a] = saved;
+    return rc;
+  }
+  c->tuned[a] = best;
+  c->have_tuned[a] = true;
+  if (best_out) *best_out = best;
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (!f) return XDROP_E_INVALID;
+    std::fprintf(f,
+                 "{\"arch\": \"gfx950\", \"alphabet\": %d, \"X\": %d, "
+                 "\"n_seeds\": %d, \"variant\": %d, \"tile\": %d, "
+                 "\"chunk\": %d, \"waves_per_cu\": %d, \"ms\": %.4f}\n",
+                 a, sc->X, n_seeds, best.variant, best.tile, best.chunk,
+                 best.waves_per_cu, best_ms);
+    std::fclose(f);
+  }
+  return XDROP_OK;
+}
+
+namespace {
+bool json_int(const std::string& line, const char* key, int* out) {
+  const std::string k = std::string("\"") + key + "\":";
+  size_t p = line.find(k);
+  if (p == std::string::npos) return false;
+  return std::sscanf(line.c_str() + p + k.size(), " %d", out) == 1;
+}
+}  // namespace
+
+extern "C" int xdrop_load_tuning(xdrop_ctx* c, const char* cache_path) {
+  if (!c || !cache_path) return XDROP_E_INVALID;
+  FILE* f = std::fopen(cache_path, "r");
+  if (!f) return XDROP_E_INVALID;
+  char buf[1024];
+  int loaded = 0;
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string line(buf);
+    if (line.find("\"gfx950\"") == std::string::npos) continue;
+    int a, v, t, ch, w = 0;
+    if (!json_int(line, "alphabet", &a) || !json_int(line, "variant", &v) ||
+        !json_int(line, "tile", &t) || !json_int(line, "chunk", &ch))
+      continue;
+    json_int(line, "waves_per_cu", &w);
+    if (a < 0 || a > 1) continue;
+    xdrop_options o{};
+    o.variant = v; o.tile = t; o.chunk = ch; o.waves_per_cu = w;
+    if (check_options(&o) != XDROP_OK) continue;
+    c->tuned[a] = o;
+    c->have_tuned[a] = true;
+    ++loaded;
+  }
+  std::fclose(f);
+  return loaded ? XDROP_OK : XDROP_E_INVALID;
+}

@@ -1,0 +1,106 @@
+// Internal definitions shared by the host side and the HIP kernels of the
+// X-Drop library (not part of the public ABI).
+#pragma once
+#include <stdint.h>
+
+namespace xd {
+
+// -infinity sentinel.  Stored values live in the frame V = S - gap * d (see
+// the kernels); every finite V satisfies |V| <= 2^28 (checked per extension),
+// so NEG plus any score entry stays far below every finite value and below
+// the lowest prune threshold THR_FLOOR.
+constexpr int32_t NEG = -(1 << 30);
+constexpr int32_t THR_FLOOR = -(1 << 29);
+constexpr int64_t VALUE_LIMIT = int64_t(1) << 28;
+constexpr int32_t X_CLAMP = 1 << 30;  // X >= 2^30 acts as infinity
+constexpr int32_t MAX_ENTRY = 1024;   // |matrix entry|, |gap| bound
+
+constexpr int WAVE = 64;
+constexpr int WPB = 4;                // waves per block of the wave kernels
+constexpr int TABLE_DIM = 32;         // substitution table is 32 x 32
+constexpr int GEN_THREADS = 256;      // general (workgroup) tier block size
+constexpr int GEN_CAP = 1 << 18;      // general tier band capacity (cells)
+
+// Per-extension result written by the extension kernels.
+struct ItemResult {
+  int32_t best, x, y, status;
+  int64_t cells;
+};
+
+// Kernel flags.
+enum : int32_t {
+  F_PLAIN = 1,      // one wave per extension, no queue
+  F_ORDERED = 2,    // items[] holds the processing order
+};
+
+// Per-seed / per-item status values (mirror the public enum).
+enum : int32_t {
+  S_OK = 0,
+  S_RANGE = -2,
+  S_SYMBOL = -6,
+  S_BAND = -7,
+};
+
+// Launch parameters of one batch (kernel argument, < 4 KiB).
+struct Params {
+  const uint32_t* seqs;      // packed stream as 32-bit words
+  const int64_t* offsets;    // n_seqs + 1
+  const int32_t* seeds;      // 5 int32 per seed
+  ItemResult* items;         // 2 * n_seeds
+  const int32_t* order;      // processing order (F_ORDERED) or null
+  int32_t* counters;         // queue heads and tier statistics
+  const uint8_t* seq_bad;    // per-sequence symbol check (BYTE) or null
+  int32_t* wide_queue;       // items handed to the 16-cell tier
+  int32_t* gen_queue;        // items handed to the general tier
+  int32_t* gen_scratch;      // general tier rings
+  int32_t n_seqs;
+  int32_t n_seeds;
+  int32_t n_items;
+  int32_t flags;
+  int32_t alphabet;          // 0 = DNA2, 1 = BYTE
+  int32_t tile;              // starting cells per lane
+  int32_t chunk;             // items per queue claim
+  int32_t band_cap;          // 0 = none
+  int32_t gap;
+  int32_t X;                 // clamped to X_CLAMP
+  int32_t mat_s, mis_s;      // DNA: match - 2 gap, mismatch - 2 gap
+  int32_t max_abs;           // max |entry| + 2 |gap|  (value bound per d)
+  int32_t gen_slots;         // concurrent general-tier workgroups
+  int16_t table[TABLE_DIM * TABLE_DIM];  // BYTE: sim - 2 gap, row = query
+};
+
+// Counter layout (int32 slots).
+enum {
+  C_HEAD = 0,       // main queue head
+  C_GEN_TAIL = 1,   // general queue tail
+  C_GEN_HEAD = 2,   // general queue head
+  C_WIDE_TAIL = 3,  // 16-cell tier queue tail
+  C_WIDE_HEAD = 4,  // 16-cell tier queue head
+  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8,16, general
+  C_HIST = 16,      // longest-first ordering: bucket sizes
+  C_CURSOR = C_HIST + 256,  // bucket write cursors
+  C_COUNT = C_CURSOR + 256
+};
+constexpr int NBUCKET = 256;
+
+}  // namespace xd
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace xd {
+hipError_t launch_reset(int32_t* counters, hipStream_t s);
+hipError_t launch_validate(const uint8_t* seqs, const int64_t* offsets,
+                           int32_t n_seqs, int32_t asize, uint8_t* bad,
+                           int grid, hipStream_t s);
+hipError_t launch_order(const int32_t* seeds, const int64_t* offsets,
+                        int32_t n_seqs, int32_t n_items, int32_t* counters,
+                        int32_t* order, int num_cu, hipStream_t s);
+hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
+                             int32_t* counters, int32_t tail_slot,
+                             hipStream_t s);
+hipError_t launch_wave(const Params& P, int cmax, int grid, hipStream_t s);
+hipError_t launch_general(const Params& P, int grid, hipStream_t s);
+hipError_t launch_combine(const Params& P, void* out, hipStream_t s);
+int wave_blocks_per_cu(int alphabet, int cmax);
+}  // namespace xd

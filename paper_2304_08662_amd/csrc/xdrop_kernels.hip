@@ -1,0 +1,980 @@
+// X-Drop seed extension kernels for gfx950 (CDNA4, wave64).
+//
+// One extension E(a, b) is the antidiagonal sweep of the paper's Sec. 3 /
+// Algorithm 1: cells (x, y) with d = x + y are filled antidiagonal by
+// antidiagonal from the two previous ones (three rolling antidiagonals);
+// a cell below T - X (T = best score of all earlier antidiagonals, strict '<')
+// is set to -infinity (Sec. 2.2 X-Drop rule); the band [lo_d, hi_d] is the
+// span reachable from the finite cells of antidiagonals d-1 and d-2, and the
+// sweep stops once both hold no finite cell.
+//
+// MI355X mapping (what differs from the paper's IPU codelet):
+//  * one wavefront per extension; the band window of 64*C cells lives in
+//    VGPRs, lane l holding window positions l*C .. l*C+C-1 (blocked), so the
+//    x-1 neighbour is the previous register of the same lane except for j = 0,
+//    which comes from lane l-1 by one DPP wave_shr:1 per antidiagonal;
+//  * values are kept in the frame V = S - gap*d, which removes both gap adds:
+//      V_d[x] = max(V_{d-1}[x-1], V_{d-1}[x], V_{d-2}[x-1] + sim - 2*gap);
+//  * pruning, the running best T (wave max reduction only on antidiagonals
+//    where some lane beats T, detected with a ballot) and the finite range
+//    (L, U) come from per-register ballots;
+//  * the window slides up by one lane (C cells) when the band reaches its top
+//    and the bottom lane is dead; when the band is wider than the window the
+//    tile widens in place (C -> 2C, registers redistributed with
+//    ds_bpermute) up to C = 16 (1024 cells); wider bands go to a workgroup
+//    tier with rings in device memory;
+//  * sequences stream through per-wave LDS rings (2-bit DNA or byte codes),
+//    read backwards for left extensions (the paper's op() transform);
+//  * extensions are pulled from a device queue by persistent waves.
+// All arithmetic is int32 integer VALU/SALU; no MFMA.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "xdrop_internal.h"
+
+namespace xd {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Lane l receives lane l-1's value; lane 0 receives `fill`.
+__device__ __forceinline__ int wave_shr1(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);
+}
+// Lane l receives lane l+1's value; lane 63 receives `fill`.
+__device__ __forceinline__ int wave_shl1(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
+}
+
+// Maximum over the wave, returned as a uniform value.
+__device__ __forceinline__ int wave_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
+  int r0 = __builtin_amdgcn_readlane(v, 0);
+  int r1 = __builtin_amdgcn_readlane(v, 16);
+  int r2 = __builtin_amdgcn_readlane(v, 32);
+  int r3 = __builtin_amdgcn_readlane(v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) {
+  return __ballot(p);
+}
+
+__device__ __forceinline__ int uni(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo,
+                                           uint32_t sh) {
+  return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// Reverse the sixteen 2-bit fields of a word.
+__device__ __forceinline__ uint32_t rev2(uint32_t v) {
+  uint32_t r = __builtin_bitreverse32(v);
+  return ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+}
+
+// Packed sequence stream; word reads are clamped to the stream, so reads
+// past either end of a sequence return other symbols (never used by a finite
+// cell) instead of leaving the buffer.
+struct Src {
+  const uint32_t* w;
+  int64_t tw;  // readable words
+};
+
+__device__ __forceinline__ Src make_src(const Params& P) {
+  const int64_t syms = P.offsets[P.n_seqs];
+  Src s;
+  s.w = P.seqs;
+  s.tw = P.alphabet == 0 ? (syms + 15) >> 4 : (syms + 3) >> 2;
+  if (s.tw < 1) s.tw = 1;
+  return s;
+}
+
+__device__ __forceinline__ uint32_t load_word(const Src& S, int64_t w) {
+  w = w < 0 ? 0 : (w >= S.tw ? S.tw - 1 : w);
+  return S.w[w];
+}
+
+// ------------------------------------------------------------------ rings
+// A ring holds elements [loaded - RS, loaded) of one extension sequence
+// (element e = source symbol start + dir * e), element e at position
+// e mod RS.  Extra words past the end mirror the first words so that reads
+// of a few consecutive words never wrap.
+template <int ALPHA>
+struct Ring;
+
+template <>
+struct Ring<0> {  // 2-bit DNA
+  static constexpr int RS = 4096;          // elements
+  static constexpr int RW = RS / 16;       // words
+  static constexpr int MIRROR = 1;
+  static constexpr int WORDS = RW + MIRROR;
+  static constexpr int CH = 1024;          // elements per fill (16 per lane)
+
+  __device__ static void fill(uint32_t* ring, const Src& S, int64_t start,
+                              int dir, int c0) {
+    const int l = lane_id();
+    int64_t e0 = (int64_t)c0 + 16 * l;
+    uint32_t v;
+    if (dir > 0) {
+      int64_t p = start + e0;
+      int64_t w = p >> 4;
+      uint32_t sh = (uint32_t)(p & 15) * 2;
+      v = funnel(load_word(S, w + 1), load_word(S, w), sh);
+    } else {
+      int64_t p = start - e0 - 15;
+      int64_t w = p >> 4;
+      uint32_t sh = (uint32_t)(p & 15) * 2;
+      v = rev2(funnel(load_word(S, w + 1), load_word(S, w), sh));
+    }
+    int wi = ((c0 >> 4) + l) & (RW - 1);
+    ring[wi] = v;
+    if (wi < MIRROR) ring[RW + wi] = v;
+  }
+  // 2*C bits: element e0 + k at bits 2k (k < C <= 16).
+  __device__ static uint32_t read(const uint32_t* ring, int e0) {
+    int pos = e0 & (RS - 1);
+    int w = pos >> 4;
+    uint32_t sh = (uint32_t)(pos & 15) * 2;
+    return funnel(ring[w + 1], ring[w], sh);
+  }
+};
+
+template <>
+struct Ring<1> {  // one byte per code
+  static constexpr int RS = 2048;
+  static constexpr int RW = RS / 4;
+  static constexpr int MIRROR = 5;
+  static constexpr int WORDS = RW + MIRROR;
+  static constexpr int CH = 512;           // 8 per lane
+
+  __device__ static void fill(uint32_t* ring, const Src& S, int64_t start,
+                              int dir, int c0) {
+    const int l = lane_id();
+    int64_t e0 = (int64_t)c0 + 8 * l;
+    uint32_t v0, v1;
+    if (dir > 0) {
+      int64_t p = start + e0;
+      int64_t w = p >> 2;
+      uint32_t sh = (uint32_t)(p & 3) * 8;
+      uint32_t w0 = load_word(S, w), w1 = load_word(S, w + 1),
+               w2 = load_word(S, w + 2);
+      v0 = funnel(w1, w0, sh);
+      v1 = funnel(w2, w1, sh);
+    } else {
+      int64_t p = start - e0 - 7;
+      int64_t w = p >> 2;
+      uint32_t sh = (uint32_t)(p & 3) * 8;
+      uint32_t w0 = load_word(S, w), w1 = load_word(S, w + 1),
+               w2 = load_word(S, w + 2);
+      uint32_t lo = funnel(w1, w0, sh), hi = funnel(w2, w1, sh);
+      v0 = __builtin_bswap32(hi);
+      v1 = __builtin_bswap32(lo);
+    }
+    int wi = ((c0 >> 2) + 2 * l) & (RW - 1);
+    ring[wi] = v0;
+    ring[wi + 1] = v1;
+    if (wi < MIRROR) ring[RW + wi] = v0;
+    if (wi + 1 < MIRROR) ring[RW + wi + 1] = v1;
+  }
+  // NW words: element e0 + k at byte k (k < 4*NW).
+  template <int NW>
+  __device__ static void read(const uint32_t* ring, int e0, uint32_t (&out)[NW]) {
+    int pos = e0 & (RS - 1);
+    int w = pos >> 2;
+    uint32_t sh = (uint32_t)(pos & 3) * 8;
+    uint32_t prev = ring[w];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      uint32_t nx = ring[w + i + 1];
+      out[i] = funnel(nx, prev, sh);
+      prev = nx;
+    }
+  }
+};
+
+// ------------------------------------------------------------------ state
+// Scalar (wave-uniform) state of one extension.
+struct Ext {
+  int m, n;           // lengths of a and b
+  int64_t a_start, b_start;
+  int a_dir, b_dir;
+  int d;              // next antidiagonal to compute
+  int base;           // window position 0 is x = base
+  int T, bx, by;      // best score (S frame) and its cell
+  int L1, U1, alive1; // finite range of d-1
+  int L2, U2, alive2; // finite range of d-2
+  int64_t W;          // live-span cells so far
+  int loaded_a, loaded_b;  // ring fill levels (elements)
+};
+
+enum { R_CONT = 0, R_DONE = 1, R_ESC = 2, R_CAP = 3 };
+
+template <int ALPHA>
+struct WaveLds {
+  uint32_t ra[Ring<ALPHA>::WORDS];
+  uint32_t rb[Ring<ALPHA>::WORDS];
+};
+
+// Query-side symbols of a lane's C cells (depend only on base and C).
+template <int ALPHA, int C>
+struct ASyms;
+
+template <int C>
+struct ASyms<0, C> {
+  uint32_t f;  // cell j at 2-bit field C-1-j
+  __device__ void load(const WaveLds<0>& w, int base) {
+    uint32_t v = Ring<0>::read(w.ra, base + lane_id() * C - 1);
+    f = rev2(v) >> (32 - 2 * C);
+  }
+};
+
+template <int C>
+struct ASyms<1, C> {
+  int row[C];  // 32 * code of cell j's query symbol
+  __device__ void load(const WaveLds<1>& w, int base) {
+    constexpr int NW = (C + 3) / 4;
+    uint32_t v[NW];
+    Ring<1>::read<NW>(w.ra, base + lane_id() * C - 1, v);
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) << 5;
+  }
+};
+
+template <int ALPHA>
+__device__ __forceinline__ void cover_a(Ext& e, WaveLds<ALPHA>& w,
+                                        const Src& P, int need_hi) {
+  // make element need_hi (and everything below it down to the window)
+  // available
+  while (e.loaded_a <= need_hi) {
+    Ring<ALPHA>::fill(w.ra, P, e.a_start, e.a_dir, e.loaded_a);
+    e.loaded_a += Ring<ALPHA>::CH;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int ALPHA>
+__device__ __forceinline__ void cover_b(Ext& e, WaveLds<ALPHA>& w,
+                                        const Src& P, int need_hi) {
+  while (e.loaded_b <= need_hi) {
+    Ring<ALPHA>::fill(w.rb, P, e.b_start, e.b_dir, e.loaded_b);
+    e.loaded_b += Ring<ALPHA>::CH;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------------ step
+// Computes antidiagonal e.d into `cur` (which holds d-2 on entry) from
+// `prev` (d-1).  On R_CONT the caller swaps the roles of the two arrays.
+template <int ALPHA, int C>
+__device__ __forceinline__ int step(Ext& e, int (&prev)[C], int (&cur)[C],
+                                    ASyms<ALPHA, C>& as, WaveLds<ALPHA>& w,
+                                    const int* tab, const Params& P,
+                                    const Src& S) {
+  const int lane = lane_id();
+  const int d = e.d;
+
+  // span of this antidiagonal (live-span count, band cap)
+  {
+    int lo = 0x7fffffff, hi = -0x7fffffff;
+    if (e.alive1) { lo = min(lo, e.L1); hi = max(hi, e.U1 + 1); }
+    if (e.alive2) { lo = min(lo, e.L2 + 1); hi = max(hi, e.U2 + 1); }
+    lo = max(lo, max(0, d - e.n));
+    hi = min(hi, min(e.m, d));
+    if (hi >= lo) {
+      e.W += hi - lo + 1;
+      if (P.band_cap > 0 && hi - lo + 1 > P.band_cap) return R_CAP;
+    }
+  }
+
+  // target-side symbols of this step: cell j of lane l has b element
+  // d - base - l*C - 1 - j
+  cover_b<ALPHA>(e, w, S, d - e.base - 1);
+  const int yb = d - e.base - lane * C - 1;
+
+  int s[C];
+  if constexpr (ALPHA == 0) {
+    uint32_t bf = Ring<0>::read(w.rb, yb - C + 1);  // cell j at field C-1-j
+    uint32_t x = bf ^ as.f;
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      s[j] = ((x >> (2 * (C - 1 - j))) & 3u) ? P.mis_s : P.mat_s;
+  } else {
+    constexpr int NW = (C + 3) / 4;
+    uint32_t bw[NW];
+    Ring<1>::read<NW>(w.rb, yb - C + 1, bw);  // cell j at byte C-1-j
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = C - 1 - j;
+      int bc = (int)((bw[k >> 2] >> (8 * (k & 3))) & 31u);
+      s[j] = tab[as.row[j] + bc];
+    }
+  }
+
+  // neighbours from the lane below (window position l*C - 1)
+  const int up0 = wave_shr1(prev[C - 1], NEG);
+  const int dg0 = wave_shr1(cur[C - 1], NEG);
+
+  // thresholds in the V frame: S >= T - X  <=>  V >= T - X - gap*d
+  int thr = e.T - P.X - P.gap * d;
+  thr = max(thr, THR_FLOOR);
+  const int pmin = d - e.n - e.base;  // positions below: y > n
+  const int pmax = e.m - e.base;      // positions above: x > m
+  const bool edge = (pmin > 0) | (pmax < 64 * C - 1);
+
+  int v[C];
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const int up = j ? prev[j - 1] : up0;
+    const int dg = j ? cur[j - 1] : dg0;
+    v[j] = max(max(up, prev[j]), dg + s[j]);
+  }
+  if (edge) {
+    const int p0 = lane * C;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int p = p0 + j;
+      if (p < pmin || p > pmax) v[j] = NEG;
+    }
+  }
+  uint64_t msk[C];
+  uint64_t any = 0;
+  int lm = NEG;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const bool f = v[j] >= thr;
+    cur[j] = f ? v[j] : NEG;
+    msk[j] = ballot(f);
+    any |= msk[j];
+    lm = max(lm, cur[j]);
+  }
+
+  // running best (S frame value T <=> V frame value T - gap*d)
+  const int Tv = e.T - P.gap * d;
+  if (ballot(lm > Tv)) {
+    const int wm = wave_max(lm);
+    const uint64_t eq = ballot(lm == wm);
+    const int l0 = __builtin_ctzll(eq);
+    int jf = C - 1;
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j)
+      if (cur[j] == wm) jf = j;
+    const int js = __builtin_amdgcn_readlane(jf, l0);
+    e.T = wm + P.gap * d;
+    e.bx = e.base + l0 * C + js;
+    e.by = d - e.bx;
+  }
+
+  // finite range of d
+  int alive0 = any != 0, L0 = 0, U0 = 0;
+  if (alive0) {
+    const int llo = __builtin_ctzll(any);
+    const int lhi = 63 - __builtin_clzll(any);
+    int jlo = 0, jhi = 0;
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j)
+      if ((msk[j] >> llo) & 1) jlo = j;
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if ((msk[j] >> lhi) & 1) jhi = j;
+    L0 = e.base + llo * C + jlo;
+    U0 = e.base + lhi * C + jhi;
+  }
+
+  const int alive1 = e.alive1, L1 = e.L1, U1 = e.U1;
+  e.L2 = e.L1; e.U2 = e.U1; e.alive2 = e.alive1;
+  e.L1 = L0; e.U1 = U0; e.alive1 = alive0;
+  e.d = d + 1;
+  if ((!alive0 && !alive1) || d >= e.m + e.n) return R_DONE;
+
+  // keep the next antidiagonal's band inside the window
+  int hi_next = -0x7fffffff;
+  if (alive0) hi_next = U0 + 1;
+  if (alive1) hi_next = max(hi_next, U1 + 1);
+  hi_next = min(hi_next, min(e.m, d + 1));
+  const int top = e.base + 64 * C - 1;
+  if (hi_next > top) {
+    int lo_fin = 0x7fffffff;
+    if (alive0) lo_fin = L0;
+    if (alive1) lo_fin = min(lo_fin, L1);
+    if (e.base + C > lo_fin) return R_ESC;
+    // slide the window up by one lane
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      cur[j] = wave_shl1(cur[j], NEG);
+      prev[j] = wave_shl1(prev[j], NEG);
+    }
+    e.base += C;
+    cover_a<ALPHA>(e, w, S, e.base + 64 * C - 2);
+    as.load(w, e.base);
+  }
+  return R_CONT;
+}
+
+// Redistribute a window of C cells per lane into 2C cells per lane
+// (same base; the upper half of the new window starts at -infinity).
+template <int C>
+__device__ __forceinline__ void widen(const int (&src)[C], int (&dst)[2 * C]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < 2 * C; ++j) {
+    const int sl = 2 * lane + j / C;
+    const int v = __builtin_amdgcn_ds_bpermute((sl & 63) << 2, src[j % C]);
+    dst[j] = sl < 64 ? v : NEG;
+  }
+}
+
+// Runs tier C (64*C cells per window) and widens in place (C -> 2C) while
+// the band outgrows the window, up to CMAX.  A holds d-1 and B holds d-2 on
+// entry.  The first call may ask for a wider starting tile (start > C); the
+// state is then still the initial one and is widened before any step.
+template <int ALPHA, int C, int CMAX>
+__device__ int run_tier(Ext& e, int (&A)[C], int (&B)[C], WaveLds<ALPHA>& w,
+                        const int* tab, const Params& P, const Src& S,
+                        int start, int& tier_out) {
+  int r = R_ESC;
+  bool newest_in_B = false;
+  if (start <= C) {
+    ASyms<ALPHA, C> as;
+    cover_a<ALPHA>(e, w, S, e.base + 64 * C - 2);
+    as.load(w, e.base);
+    for (;;) {
+      r = step<ALPHA, C>(e, A, B, as, w, tab, P, S);
+      if (r != R_CONT) { newest_in_B = true; break; }
+      r = step<ALPHA, C>(e, B, A, as, w, tab, P, S);
+      if (r != R_CONT) { newest_in_B = false; break; }
+    }
+  }
+  if constexpr (C < CMAX) {
+    if (r == R_ESC) {
+      int N1[2 * C], N2[2 * C];
+      if (newest_in_B) { widen<C>(B, N1); widen<C>(A, N2); }
+      else { widen<C>(A, N1); widen<C>(B, N2); }
+      return run_tier<ALPHA, 2 * C, CMAX>(e, N1, N2, w, tab, P, S, start,
+                                          tier_out);
+    }
+  }
+  tier_out = C;
+  return r;
+}
+
+template <int ALPHA, int CMIN, int CMAX>
+__device__ int start_tier(Ext& e, WaveLds<ALPHA>& w, const int* tab,
+                          const Params& P, const Src& S, int start,
+                          int& tier_out) {
+  int A[CMIN], B[CMIN];
+#pragma unroll
+  for (int j = 0; j < CMIN; ++j) { A[j] = NEG; B[j] = NEG; }
+  if (lane_id() == 0) A[0] = 0;  // S(0,0) = 0 at window position 0
+  return run_tier<ALPHA, CMIN, CMAX>(e, A, B, w, tab, P, S, start, tier_out);
+}
+
+// ------------------------------------------------------------------ items
+struct ItemSetup {
+  int status;
+  Ext e;
+};
+
+__device__ __forceinline__ ItemSetup setup_item(const Params& P, int item) {
+  ItemSetup s;
+  s.status = S_OK;
+  const int seed = item >> 1;
+  const int right = item & 1;
+  const int* sd = P.seeds + 5 * (int64_t)seed;
+  const int q = sd[0], t = sd[1], qp = sd[2], tp = sd[3], k = sd[4];
+  Ext& e = s.e;
+  e.m = e.n = 0;
+  if (q < 0 || q >= P.n_seqs || t < 0 || t >= P.n_seqs) {
+    s.status = S_RANGE;
+    return s;
+  }
+  const int64_t oq = P.offsets[q], lq = P.offsets[q + 1] - oq;
+  const int64_t ot = P.offsets[t], lt = P.offsets[t + 1] - ot;
+  if (k < 0 || qp < 0 || tp < 0 || qp + (int64_t)k > lq ||
+      tp + (int64_t)k > lt) {
+    s.status = S_RANGE;
+    return s;
+  }
+  if (P.seq_bad && (P.seq_bad[q] | P.seq_bad[t])) {
+    s.status = S_SYMBOL;
+    return s;
+  }
+  int64_t m, n;
+  if (!right) {
+    m = qp; n = tp;
+    e.a_start = oq + qp - 1; e.b_start = ot + tp - 1;
+    e.a_dir = -1; e.b_dir = -1;
+  } else {
+    m = lq - qp - k; n = lt - tp - k;
+    e.a_start = oq + qp + k; e.b_start = ot + tp + k;
+    e.a_dir = 1; e.b_dir = 1;
+  }
+  if ((m + n) * (int64_t)P.max_abs > VALUE_LIMIT ||
+      k * (int64_t)P.max_abs > VALUE_LIMIT) {
+    s.status = S_RANGE;
+    return s;
+  }
+  e.m = (int)m; e.n = (int)n;
+  e.d = 1; e.base = 0;
+  e.T = 0; e.bx = 0; e.by = 0;
+  e.L1 = 0; e.U1 = 0; e.alive1 = 1;  // antidiagonal 0: S(0,0) = 0
+  e.L2 = 0; e.U2 = 0; e.alive2 = 0;
+  e.W = 1;
+  e.loaded_a = 0; e.loaded_b = 0;
+  return s;
+}
+
+__device__ __forceinline__ int tier_index(int C) {
+  return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : C == 8 ? 3 : 4;
+}  // the general tier counts at index 5
+
+template <int ALPHA, int CMIN, int CMAX>
+__device__ void run_item(const Params& P, const Src& S, int item,
+                         WaveLds<ALPHA>& w, const int* tab) {
+  ItemSetup s = setup_item(P, item);
+  ItemResult res;
+  res.best = 0; res.x = 0; res.y = 0; res.status = s.status; res.cells = 0;
+  bool handed_on = false;
+  if (s.status == S_OK) {
+    Ext& e = s.e;
+    int r = R_DONE, tier = CMIN;
+    if (e.m + e.n != 0) {
+      const int start = CMIN > P.tile ? CMIN : P.tile;
+      r = start_tier<ALPHA, CMIN, CMAX>(e, w, tab, P, S, start, tier);
+    }
+    if (r == R_ESC) {
+      // band wider than this kernel's widest window: restart the extension
+      // in the next tier
+      handed_on = true;
+      if (lane_id() == 0) {
+        if (CMAX < 16) {
+          const int slot = atomicAdd(P.counters + C_WIDE_TAIL, 1);
+          P.wide_queue[slot] = item;
+        } else {
+          const int slot = atomicAdd(P.counters + C_GEN_TAIL, 1);
+          P.gen_queue[slot] = item;
+        }
+      }
+    } else if (r == R_CAP) {
+      res.status = S_BAND;
+    } else {
+      res.best = e.T; res.x = e.bx; res.y = e.by; res.cells = e.W;
+      if (lane_id() == 0)
+        atomicAdd(P.counters + C_TIER0 + tier_index(tier), 1);
+    }
+  }
+  if (!handed_on && lane_id() == 0) P.items[item] = res;
+}
+
+// Persistent wave kernels.  CMAX = 8: extensions of the batch, pulled from
+// the queue in chunks of P.chunk (or, in the plain form, one per launched
+// wave), tiles 1..8 cells per lane.  CMAX = 16: the extensions handed on by
+// the first kernel, restarted with 16 cells per lane.
+template <int ALPHA, int CMAX>
+__global__ __launch_bounds__(WAVE * WPB) void xd_wave_kernel(Params P) {
+  constexpr int CMIN = CMAX == 16 ? 16 : 1;
+  __shared__ WaveLds<ALPHA> lds[WPB];
+  __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
+  if constexpr (ALPHA == 1) {
+    for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
+      tab[i] = P.table[i];
+    __syncthreads();
+  }
+  const int wid = threadIdx.x >> 6;
+  WaveLds<ALPHA>& w = lds[wid];
+  const Src S = make_src(P);
+  if (CMAX == 16) {
+    const int n = uni(__hip_atomic_load(P.counters + C_WIDE_TAIL,
+                                        __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT));
+    for (;;) {
+      int c = 0;
+      if (lane_id() == 0) c = atomicAdd(P.counters + C_WIDE_HEAD, 1);
+      c = uni(c);
+      if (c >= n) break;
+      run_item<ALPHA, CMIN, CMAX>(P, S, uni(P.wide_queue[c]), w, tab);
+    }
+    return;
+  }
+  if (P.flags & F_PLAIN) {
+    const int idx = uni(blockIdx.x * WPB + wid);
+    if (idx < P.n_items)
+      run_item<ALPHA, CMIN, CMAX>(
+          P, S, (P.flags & F_ORDERED) ? uni(P.order[idx]) : idx, w, tab);
+    return;
+  }
+  int cur = 0, end = 0;
+  for (;;) {
+    if (cur >= end) {
+      int c = 0;
+      if (lane_id() == 0) c = atomicAdd(P.counters + C_HEAD, P.chunk);
+      cur = uni(c);
+      end = min(cur + P.chunk, P.n_items);
+      if (cur >= P.n_items) break;
+    }
+    const int idx = cur++;
+    const int item = (P.flags & F_ORDERED) ? uni(P.order[idx]) : idx;
+    run_item<ALPHA, CMIN, CMAX>(P, S, item, w, tab);
+  }
+}
+
+// ------------------------------------------------------------------ general
+// Workgroup-per-extension tier for bands wider than the register window:
+// antidiagonals d, d-1, d-2 in three rings of GEN_CAP cells in device memory
+// (cell x at x mod GEN_CAP), every cell of [lo_d, hi_d] computed by the
+// GEN_THREADS threads of the block, reductions through LDS.
+
+__device__ __forceinline__ int sym_at(const Params& P, const Src& S,
+                                      int64_t pos) {
+  if (P.alphabet == 0) {
+    uint32_t wv = load_word(S, pos >> 4);
+    return (int)((wv >> (2 * (pos & 15))) & 3u);
+  }
+  uint32_t wv = load_word(S, pos >> 2);
+  return (int)((wv >> (8 * (pos & 3))) & 31u);
+}
+
+__global__ __launch_bounds__(GEN_THREADS) void xd_general_kernel(Params P) {
+  __shared__ int s_max, s_x, s_L, s_U, s_item;
+  __shared__ int tab[TABLE_DIM * TABLE_DIM];
+  for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
+    tab[i] = P.table[i];
+  const Src S = make_src(P);
+  int* ring[3];
+  for (int r = 0; r < 3; ++r)
+    ring[r] = P.gen_scratch + ((int64_t)blockIdx.x * 3 + r) * GEN_CAP;
+  const int tid = threadIdx.x;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) {
+      int h = atomicAdd(P.counters + C_GEN_HEAD, 1);
+      s_item = h < atomicAdd(P.counters + C_GEN_TAIL, 0) ? P.gen_queue[h] : -1;
+    }
+    __syncthreads();
+    const int item = s_item;
+    if (item < 0) break;
+    ItemSetup st = setup_item(P, item);
+    Ext& e = st.e;
+    ItemResult res;
+    res.best = 0; res.x = 0; res.y = 0; res.cells = 1; res.status = st.status;
+    // antidiagonal ranges: computed span [lo, hi] and finite range [L, U]
+    int lo1 = 0, hi1 = 0, lo2 = 1, hi2 = 0;  // d-1 = 0 holds x = 0 only
+    if (tid == 0) ring[0][0] = 0;
+    int T = 0, bx = 0, by = 0;
+    int64_t W = 1;
+    int alive1 = 1, L1 = 0, U1 = 0, alive2 = 0, L2 = 0, U2 = 0;
+    int r1 = 0, r2 = 2, r0 = 1;  // ring indices of d-1, d-2, d
+    for (int d = 1; d <= e.m + e.n && (alive1 || alive2); ++d) {
+      int lo = 0x7fffffff, hi = -0x7fffffff;
+      if (alive1) { lo = min(lo, L1); hi = max(hi, U1 + 1); }
+      if (alive2) { lo = min(lo, L2 + 1); hi = max(hi, U2 + 1); }
+      lo = max(lo, max(0, d - e.n));
+      hi = min(hi, min(e.m, d));
+      const int thr = max(T - P.X - P.gap * d, THR_FLOOR);
+      __syncthreads();
+      if (tid == 0) { s_max = NEG; s_x = 0x7fffffff; s_L = 0x7fffffff; s_U = -1; }
+      __syncthreads();
+      if (hi >= lo) {
+        W += hi - lo + 1;
+        if ((P.band_cap > 0 && hi - lo + 1 > P.band_cap) ||
+            hi - lo + 1 > GEN_CAP) {
+          res.status = S_BAND;
+          break;
+        }
+      }
+      const int* R1 = ring[r1];
+      const int* R2 = ring[r2];
+      int* R0 = ring[r0];
+      int tmax = NEG, tL = 0x7fffffff, tU = -1;
+      for (int x = lo + tid; x <= hi; x += GEN_THREADS) {
+        const int y = d - x;
+        int v = NEG;
+        if (x >= 1 && x - 1 >= lo1 && x - 1 <= hi1)
+          v = max(v, R1[(x - 1) & (GEN_CAP - 1)]);
+        if (y >= 1 && x >= lo1 && x <= hi1)
+          v = max(v, R1[x & (GEN_CAP - 1)]);
+        if (x >= 1 && y >= 1 && x - 1 >= lo2 && x - 1 <= hi2) {
+          const int ca = sym_at(P, S, e.a_start + (int64_t)e.a_dir * (x - 1));
+          const int cb = sym_at(P, S, e.b_start + (int64_t)e.b_dir * (y - 1));
+          int sv;
+          if (P.alphabet == 0) sv = ca == cb ? P.mat_s : P.mis_s;
+          else sv = tab[ca * TABLE_DIM + cb];
+          v = max(v, R2[(x - 1) & (GEN_CAP - 1)] + sv);
+        }
+        if (v < thr) v = NEG;
+        R0[x & (GEN_CAP - 1)] = v;
+        if (v != NEG) {
+          tL = min(tL, x);
+          tU = max(tU, x);
+          if (v > tmax) tmax = v;  // x ascending: first x kept on ties
+        }
+      }
+      atomicMax(&s_max, tmax);
+      atomicMin(&s_L, tL);
+      atomicMax(&s_U, tU);
+      __syncthreads();
+      const int gm = s_max;
+      if (gm != NEG && gm > T - P.gap * d) {
+        for (int x = lo + tid; x <= hi; x += GEN_THREADS)
+          if (R0[x & (GEN_CAP - 1)] == gm) atomicMin(&s_x, x);
+      }
+      __syncthreads();
+      if (gm != NEG && gm > T - P.gap * d) {
+        T = gm + P.gap * d;
+        bx = s_x;
+        by = d - bx;
+      }
+      alive2 = alive1; L2 = L1; U2 = U1;
+      alive1 = s_U >= 0; L1 = s_L; U1 = s_U;
+      lo2 = lo1; hi2 = hi1; lo1 = lo; hi1 = hi;
+      const int rt = r2; r2 = r1; r1 = r0; r0 = rt;
+    }
+    if (res.status == S_OK) {
+      res.best = T; res.x = bx; res.y = by; res.cells = W;
+      if (tid == 0) atomicAdd(P.counters + C_TIER0 + 5, 1);
+    } else if (res.status == S_BAND) {
+      res.best = 0; res.x = 0; res.y = 0; res.cells = 0;
+    }
+    if (tid == 0) P.items[item] = res;
+  }
+}
+
+// ------------------------------------------------------------------ misc
+// Zero the counters (a kernel rather than a memset so that the launch
+// sequence can be captured in a graph).
+__global__ void xd_reset_kernel(int32_t* counters) {
+  for (int i = threadIdx.x; i < C_COUNT; i += blockDim.x) counters[i] = 0;
+}
+
+// Symbol check for byte-coded sequences: bad[s] = any code >= asize.
+__global__ void xd_validate_kernel(const uint8_t* seqs, const int64_t* offsets,
+                                   int32_t n_seqs, int32_t asize,
+                                   uint8_t* bad) {
+  const int lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  for (int64_t s = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); s < n_seqs;
+       s += (int64_t)gridDim.x * wpb) {
+    const int64_t a = offsets[s], b = offsets[s + 1];
+    int found = 0;
+    for (int64_t i = a + lane; i < b; i += 64) found |= seqs[i] >= asize;
+    const uint64_t any = ballot(found != 0);
+    if (lane == 0) bad[s] = any != 0;
+  }
+}
+
+// Longest-first order.  The cost of an extension is m + n, the length of
+// its antidiagonal chain (its latency; the paper's batcher uses the
+// quadratic m*n, an area bound).  Extensions are bucketed on a log scale
+// (8 buckets per power of two) and scattered longest bucket first: a
+// counting sort without device-wide memsets, so it can be captured in a
+// graph.  Order inside a bucket is arbitrary (results do not depend on it).
+__device__ __forceinline__ int cost_bucket(const int32_t* seeds,
+                                           const int64_t* offsets,
+                                           int32_t n_seqs, int i) {
+  const int seed = i >> 1, right = i & 1;
+  const int* sd = seeds + 5 * (int64_t)seed;
+  const int q = sd[0], t = sd[1], qp = sd[2], tp = sd[3], k = sd[4];
+  uint32_t key = 0;
+  if (q >= 0 && q < n_seqs && t >= 0 && t < n_seqs) {
+    const int64_t lq = offsets[q + 1] - offsets[q];
+    const int64_t lt = offsets[t + 1] - offsets[t];
+    int64_t c = right ? (lq - qp - k) + (lt - tp - k) : (int64_t)qp + tp;
+    c = c < 0 ? 0 : (c > 0x7fffffff ? 0x7fffffff : c);
+    key = (uint32_t)c;
+  }
+  int f = 0;
+  if (key >= 8) {
+    const int e = 31 - __builtin_clz(key);
+    f = e * 8 + (int)((key >> (e - 3)) & 7u);
+  } else {
+    f = (int)key;
+  }
+  return NBUCKET - 1 - min(f, NBUCKET - 1);  // longest first
+}
+
+__global__ void xd_hist_kernel(const int32_t* seeds, const int64_t* offsets,
+                               int32_t n_seqs, int32_t n_items,
+                               int32_t* counters) {
+  __shared__ int h[NBUCKET];
+  for (int b = threadIdx.x; b < NBUCKET; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items;
+       i += gridDim.x * blockDim.x)
+    atomicAdd(&h[cost_bucket(seeds, offsets, n_seqs, i)], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < NBUCKET; b += blockDim.x)
+    if (h[b]) atomicAdd(counters + C_HIST + b, h[b]);
+}
+
+__global__ void xd_scan_kernel(int32_t* counters) {
+  // single block of NBUCKET threads: exclusive prefix sum into the cursors
+  __shared__ int v[NBUCKET];
+  const int b = threadIdx.x;
+  v[b] = counters[C_HIST + b];
+  __syncthreads();
+  for (int off = 1; off < NBUCKET; off <<= 1) {
+    const int add = b >= off ? v[b - off] : 0;
+    __syncthreads();
+    v[b] += add;
+    __syncthreads();
+  }
+  counters[C_CURSOR + b] = v[b] - counters[C_HIST + b];
+}
+
+__global__ void xd_scatter_kernel(const int32_t* seeds, const int64_t* offsets,
+                                  int32_t n_seqs, int32_t n_items,
+                                  int32_t* counters, int32_t* order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const int b = cost_bucket(seeds, offsets, n_seqs, i);
+  order[atomicAdd(counters + C_CURSOR + b, 1)] = i;
+}
+
+// Seed level: score = left + seed score + right and positions (Sec. 4.1.1).
+__global__ void xd_combine_kernel(Params P, void* out_v) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= P.n_seeds) return;
+  struct Out {
+    int32_t score, left, right, seed_score;
+    int32_t q_begin, q_end, t_begin, t_end;
+    int64_t cells;
+    int32_t status, reserved;
+  };
+  Out* out = (Out*)out_v;
+  const ItemResult L = P.items[2 * (int64_t)s];
+  const ItemResult R = P.items[2 * (int64_t)s + 1];
+  Out o = {};
+  int st = L.status != S_OK ? L.status : R.status;
+  if (st == S_OK) {
+    const int* sd = P.seeds + 5 * (int64_t)s;
+    const int q = sd[0], t = sd[1], qp = sd[2], tp = sd[3], k = sd[4];
+    const int64_t oq = P.offsets[q], ot = P.offsets[t];
+    const Src S = make_src(P);
+    int seed = 0;
+    for (int u = 0; u < k; ++u) {
+      const int ca = sym_at(P, S, oq + qp + u), cb = sym_at(P, S, ot + tp + u);
+      if (P.alphabet == 0) seed += (ca == cb ? P.mat_s : P.mis_s) + 2 * P.gap;
+      else seed += P.table[ca * TABLE_DIM + cb] + 2 * P.gap;
+    }
+    o.left = L.best; o.right = R.best; o.seed_score = seed;
+    o.score = L.best + seed + R.best;
+    o.q_begin = qp - L.x; o.t_begin = tp - L.y;
+    o.q_end = qp + k + R.x; o.t_end = tp + k + R.y;
+    o.cells = L.cells + R.cells;
+  }
+  o.status = st;
+  out[s] = o;
+}
+
+template __global__ void xd_wave_kernel<0, 8>(Params);
+template __global__ void xd_wave_kernel<1, 8>(Params);
+template __global__ void xd_wave_kernel<0, 16>(Params);
+template __global__ void xd_wave_kernel<1, 16>(Params);
+
+}  // namespace xd
+
+// ==================================================================== host
+// Launch wrappers used by the C ABI (xdrop_host.cpp).
+namespace xd {
+
+__global__ void xd_fill_queue_kernel(const int32_t* order, int32_t n,
+                                     int32_t* queue, int32_t* counters,
+                                     int32_t tail_slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) queue[i] = order ? order[i] : i;
+  if (i == 0) counters[tail_slot] = n;
+}
+
+hipError_t launch_reset(int32_t* counters, hipStream_t s) {
+  hipLaunchKernelGGL(xd_reset_kernel, dim3(1), dim3(256), 0, s, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const uint8_t* seqs, const int64_t* offsets,
+                           int32_t n_seqs, int32_t asize, uint8_t* bad,
+                           int grid, hipStream_t s) {
+  if (n_seqs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(xd_validate_kernel, dim3(grid), dim3(256), 0, s, seqs,
+                     offsets, n_seqs, asize, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const int32_t* seeds, const int64_t* offsets,
+                        int32_t n_seqs, int32_t n_items, int32_t* counters,
+                        int32_t* order, int num_cu, hipStream_t s) {
+  const int grid = std::min((n_items + 255) / 256, num_cu * 4);
+  hipLaunchKernelGGL(xd_hist_kernel, dim3(std::max(grid, 1)), dim3(256), 0, s,
+                     seeds, offsets, n_seqs, n_items, counters);
+  hipLaunchKernelGGL(xd_scan_kernel, dim3(1), dim3(NBUCKET), 0, s, counters);
+  hipLaunchKernelGGL(xd_scatter_kernel, dim3((n_items + 255) / 256), dim3(256),
+                     0, s, seeds, offsets, n_seqs, n_items, counters, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
+                             int32_t* counters, int32_t tail_slot,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(xd_fill_queue_kernel, dim3((n + 255) / 256 + 1),
+                     dim3(256), 0, s, order, n, queue, counters, tail_slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_wave(const Params& P, int cmax, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (P.alphabet == 0) {
+    if (cmax == 16)
+      hipLaunchKernelGGL((xd_wave_kernel<0, 16>), dim3(grid), dim3(WAVE * WPB),
+                         0, s, P);
+    else
+      hipLaunchKernelGGL((xd_wave_kernel<0, 8>), dim3(grid), dim3(WAVE * WPB),
+                         0, s, P);
+  } else {
+    if (cmax == 16)
+      hipLaunchKernelGGL((xd_wave_kernel<1, 16>), dim3(grid), dim3(WAVE * WPB),
+                         0, s, P);
+    else
+      hipLaunchKernelGGL((xd_wave_kernel<1, 8>), dim3(grid), dim3(WAVE * WPB),
+                         0, s, P);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_general(const Params& P, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(xd_general_kernel, dim3(grid), dim3(GEN_THREADS), 0, s,
+                     P);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const Params& P, void* out, hipStream_t s) {
+  if (P.n_seeds <= 0) return hipSuccess;
+  hipLaunchKernelGGL(xd_combine_kernel, dim3((P.n_seeds + 255) / 256),
+                     dim3(256), 0, s, P, out);
+  return hipGetLastError();
+}
+
+int wave_blocks_per_cu(int alphabet, int cmax) {
+  int nb = 0;
+  hipError_t e;
+  if (alphabet == 0)
+    e = cmax == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                         &nb, xd_wave_kernel<0, 16>, WAVE * WPB, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                         &nb, xd_wave_kernel<0, 8>, WAVE * WPB, 0);
+  else
+    e = cmax == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                         &nb, xd_wave_kernel<1, 16>, WAVE * WPB, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                         &nb, xd_wave_kernel<1, 8>, WAVE * WPB, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+}  // namespace xd
