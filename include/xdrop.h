@@ -52,7 +52,8 @@ typedef enum {
     XDROP_E_DEVICE = -4,   /* HIP runtime error; sticky on the context */
     XDROP_E_BUDGET = -5,   /* serving: request can never fit the budget */
     XDROP_E_SYMBOL = -6,   /* per seed: a code >= alphabet_size */
-    XDROP_BAND_OVERFLOW = -7, /* per seed: band wider than opts->band_cap */
+    XDROP_BAND_OVERFLOW = -7, /* per seed: band wider than opts->band_cap,
+                                 or than 65536 cells (workgroup tier) */
     XDROP_PENDING = 1      /* serving: request not finished yet */
 } xdrop_status;
 
@@ -123,7 +124,8 @@ int xdrop_ctx_destroy(xdrop_ctx *ctx);
 
 /* Extend every seed of a batch.
  *   d_seqs    device, packed sequence stream (encoding = scoring->alphabet);
- *             readable up to the next multiple of 16 bytes past its end
+ *             readable up to the end of the 32-bit word that holds symbol
+ *             d_offsets[n_seqs] - 1 (the library never reads further)
  *   d_offsets device, n_seqs+1 int64 symbol offsets; sequence s is symbols
  *             [d_offsets[s], d_offsets[s+1]) of the stream (no alignment
  *             requirement)
@@ -166,6 +168,19 @@ int xdrop_extend_batch_graph(xdrop_ctx *ctx, const uint8_t *d_seqs,
                              const xdrop_options *opts,
                              xdrop_result *d_results, void *stream);
 
+/* Phase timing: with timing on, every batch records HIP events on its stream
+ * around its launch phases (no host synchronisation).  xdrop_last_timing
+ * waits for the last recorded batch, writes to ms[0..n) the durations summed
+ * over all batches recorded since timing was switched on or last read --
+ * (0) counters, symbol check and longest-first ordering, (1) the wave kernel
+ * of 1..8 cells per lane, (2) the 16-cell wave kernel, (3) the workgroup
+ * tier, (4) the seed-level combine -- sets *batches (optional) to their
+ * number, and starts a new record.  Returns XDROP_E_INVALID if none was
+ * recorded. */
+int xdrop_ctx_set_timing(xdrop_ctx *ctx, int32_t on);
+int xdrop_last_timing(xdrop_ctx *ctx, float *ms, int32_t n,
+                      int32_t *batches);
+
 /* Statistics of the last batch on this context (after stream sync):
  * counts of extensions finished at each tile width (1, 2, 4, 8, 16 cells per
  * lane, workgroup tier, general tier). */
@@ -190,10 +205,15 @@ typedef struct {
 
 typedef struct {
     int32_t max_inflight;   /* requests resident at once; 0 = 256 */
-    int32_t worker_waves;   /* device waves of the resident worker; 0 = auto */
-    int32_t reserved[6];
+    int32_t streams;        /* micro-batches in flight at once; 0 = 4 */
+    int32_t arena_mib;      /* sequence arena in MiB; 0 = everything the
+                               budget leaves after the per-stream staging and
+                               workspace (40 MiB per stream) */
+    int32_t reserved[5];
 } xdrop_server_opts;
 
+/* hbm_budget_bytes bounds all device memory of the server: the sequence
+ * arena plus 40 MiB per stream.  XDROP_E_BUDGET if that does not fit. */
 int xdrop_server_create(int device, size_t hbm_budget_bytes,
                         const xdrop_server_opts *opts, xdrop_server **out);
 /* Copies the request; returns XDROP_E_BUDGET if it can never fit. */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -45,6 +46,11 @@ struct xdrop_ctx {
   bool have_tuned[2] = {false, false};
   xdrop_options tuned[2];
   std::vector<GraphEntry> graphs;
+  // phase timing (xdrop_ctx_set_timing): one set of events around the
+  // launch phases per batch, summed by xdrop_last_timing
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 6>> ev_sets;
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -227,11 +233,22 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   const bool plain = o.variant == XDROP_VARIANT_PLAIN;
   P.flags = plain ? F_PLAIN : 0;
 
+  hipEvent_t* ev = nullptr;
+  if (c->timing) {
+    if (c->ev_used == c->ev_sets.size()) {
+      std::array<hipEvent_t, 6> set{};
+      for (auto& e : set) HIP_OK(hipEventCreate(&e));
+      c->ev_sets.push_back(set);
+    }
+    ev = c->ev_sets[c->ev_used].data();
+  }
+  const bool timed = ev != nullptr;
+  if (timed) HIP_OK(hipEventRecord(ev[0], st));
   HIP_OK(launch_reset(c->counters, st));
   if (P.alphabet == 1) {
     P.seq_bad = (const uint8_t*)(ws + L.bad);
-    HIP_OK(launch_validate(d_seqs, d_offsets, n_seqs, sc->alphabet_size,
-                           (uint8_t*)(ws + L.bad),
+    HIP_OK(launch_validate(d_seqs, d_offsets, n_seqs, P.seeds, n_seeds,
+                           sc->alphabet_size, (uint8_t*)(ws + L.bad),
                            std::min(c->num_cu * 8, (n_seqs + 3) / 4 + 1), st));
   }
   if (o.order == 0 && !plain) {
@@ -252,10 +269,13 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
       bpc = std::max(1, std::min(bpc, (o.waves_per_cu + WPB - 1) / WPB));
     return c->num_cu * bpc;
   };
+  if (timed) HIP_OK(hipEventRecord(ev[1], st));
   if (o.variant == XDROP_VARIANT_WORKGROUP) {
     // every extension on the workgroup tier
     HIP_OK(launch_fill_queue(P.order, n_items, P.gen_queue, c->counters,
                              C_GEN_TAIL, st));
+    if (timed) HIP_OK(hipEventRecord(ev[2], st));
+    if (timed) HIP_OK(hipEventRecord(ev[3], st));
   } else {
     int grid;
     if (plain)
@@ -264,11 +284,18 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
       grid = std::min(persistent_grid(0),
                       (n_items + WPB * o.chunk - 1) / (WPB * o.chunk));
     HIP_OK(launch_wave(P, 8, grid, st));
+    if (timed) HIP_OK(hipEventRecord(ev[2], st));
     HIP_OK(launch_wave(P, 16, std::min(persistent_grid(1),
                                        (n_items + WPB - 1) / WPB), st));
+    if (timed) HIP_OK(hipEventRecord(ev[3], st));
   }
   HIP_OK(launch_general(P, c->gen_slots, st));
+  if (timed) HIP_OK(hipEventRecord(ev[4], st));
   HIP_OK(launch_combine(P, d_results, st));
+  if (timed) {
+    HIP_OK(hipEventRecord(ev[5], st));
+    ++c->ev_used;
+  }
   return XDROP_OK;
 }
 
@@ -324,6 +351,8 @@ int xdrop_ctx_destroy(xdrop_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->counters) (void)hipFree(c->counters);
   if (c->gen_scratch) (void)hipFree(c->gen_scratch);
+  for (auto& set : c->ev_sets)
+    for (auto& e : set) (void)hipEventDestroy(e);
   delete c;
   return XDROP_OK;
 }
@@ -338,6 +367,31 @@ int xdrop_extend_batch(xdrop_ctx* c, const uint8_t* d_seqs,
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
   return enqueue(c, d_seqs, d_offsets, n_seqs, d_seeds, n_seeds, scoring,
                  opts, d_results, (hipStream_t)stream);
+}
+
+int xdrop_ctx_set_timing(xdrop_ctx* c, int32_t on) {
+  if (!c) return XDROP_E_INVALID;
+  (void)hipSetDevice(c->device);
+  c->timing = on != 0;
+  c->ev_used = 0;
+  return XDROP_OK;
+}
+
+int xdrop_last_timing(xdrop_ctx* c, float* ms, int32_t n,
+                      int32_t* batches) {
+  if (!c || !ms || n < 0) return XDROP_E_INVALID;
+  for (int i = 0; i < n; ++i) ms[i] = 0.f;
+  if (batches) *batches = (int32_t)c->ev_used;
+  if (!c->ev_used) return XDROP_E_INVALID;
+  HIP_OK(hipEventSynchronize(c->ev_sets[c->ev_used - 1][5]));
+  for (size_t b = 0; b < c->ev_used; ++b)
+    for (int i = 0; i < n && i < 5; ++i) {
+      float t = 0.f;
+      HIP_OK(hipEventElapsedTime(&t, c->ev_sets[b][i], c->ev_sets[b][i + 1]));
+      ms[i] += t;
+    }
+  c->ev_used = 0;
+  return XDROP_OK;
 }
 
 int xdrop_last_stats(xdrop_ctx* c, int64_t* counts, int32_t n_counts) {

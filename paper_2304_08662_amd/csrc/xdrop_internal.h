@@ -19,7 +19,7 @@ constexpr int WAVE = 64;
 constexpr int WPB = 4;                // waves per block of the wave kernels
 constexpr int TABLE_DIM = 32;         // substitution table is 32 x 32
 constexpr int GEN_THREADS = 256;      // general (workgroup) tier block size
-constexpr int GEN_CAP = 1 << 18;      // general tier band capacity (cells)
+constexpr int GEN_CAP = 1 << 16;      // general tier band capacity (cells)
 
 // Per-extension result written by the extension kernels.
 struct ItemResult {
@@ -49,7 +49,7 @@ struct Params {
   ItemResult* items;         // 2 * n_seeds
   const int32_t* order;      // processing order (F_ORDERED) or null
   int32_t* counters;         // queue heads and tier statistics
-  const uint8_t* seq_bad;    // per-sequence symbol check (BYTE) or null
+  const uint8_t* seq_bad;    // per-sequence check (BYTE): 2 = bad symbol
   int32_t* wide_queue;       // items handed to the 16-cell tier
   int32_t* gen_queue;        // items handed to the general tier
   int32_t* gen_scratch;      // general tier rings
@@ -91,7 +91,8 @@ constexpr int NBUCKET = 256;
 namespace xd {
 hipError_t launch_reset(int32_t* counters, hipStream_t s);
 hipError_t launch_validate(const uint8_t* seqs, const int64_t* offsets,
-                           int32_t n_seqs, int32_t asize, uint8_t* bad,
+                           int32_t n_seqs, const int32_t* seeds,
+                           int32_t n_seeds, int32_t asize, uint8_t* state,
                            int grid, hipStream_t s);
 hipError_t launch_order(const int32_t* seeds, const int64_t* offsets,
                         int32_t n_seqs, int32_t n_items, int32_t* counters,

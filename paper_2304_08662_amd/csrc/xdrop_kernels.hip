@@ -503,7 +503,7 @@ __device__ __forceinline__ ItemSetup setup_item(const Params& P, int item) {
     s.status = S_RANGE;
     return s;
   }
-  if (P.seq_bad && (P.seq_bad[q] | P.seq_bad[t])) {
+  if (P.seq_bad && (P.seq_bad[q] == 2 || P.seq_bad[t] == 2)) {
     s.status = S_SYMBOL;
     return s;
   }
@@ -754,19 +754,37 @@ __global__ void xd_reset_kernel(int32_t* counters) {
   for (int i = threadIdx.x; i < C_COUNT; i += blockDim.x) counters[i] = 0;
 }
 
-// Symbol check for byte-coded sequences: bad[s] = any code >= asize.
+// Symbol check for byte-coded sequences, restricted to the sequences that
+// seeds reference: state[s] = 0 unreferenced, 1 referenced, 2 referenced
+// and holding a code >= asize.
+__global__ void xd_clear_bytes_kernel(uint8_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void xd_mark_kernel(const int32_t* seeds, int32_t n_seeds,
+                               int32_t n_seqs, uint8_t* state) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_seeds) return;
+  const int q = seeds[5 * (int64_t)i], t = seeds[5 * (int64_t)i + 1];
+  if (q >= 0 && q < n_seqs) state[q] = 1;
+  if (t >= 0 && t < n_seqs) state[t] = 1;
+}
+
 __global__ void xd_validate_kernel(const uint8_t* seqs, const int64_t* offsets,
                                    int32_t n_seqs, int32_t asize,
-                                   uint8_t* bad) {
+                                   uint8_t* state) {
   const int lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (int64_t s = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); s < n_seqs;
        s += (int64_t)gridDim.x * wpb) {
+    if (state[s] == 0) continue;  // uniform per wave
     const int64_t a = offsets[s], b = offsets[s + 1];
     int found = 0;
     for (int64_t i = a + lane; i < b; i += 64) found |= seqs[i] >= asize;
     const uint64_t any = ballot(found != 0);
-    if (lane == 0) bad[s] = any != 0;
+    if (lane == 0 && any) state[s] = 2;
   }
 }
 
@@ -899,11 +917,18 @@ hipError_t launch_reset(int32_t* counters, hipStream_t s) {
 }
 
 hipError_t launch_validate(const uint8_t* seqs, const int64_t* offsets,
-                           int32_t n_seqs, int32_t asize, uint8_t* bad,
+                           int32_t n_seqs, const int32_t* seeds,
+                           int32_t n_seeds, int32_t asize, uint8_t* state,
                            int grid, hipStream_t s) {
   if (n_seqs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(xd_clear_bytes_kernel,
+                     dim3(std::min((n_seqs + 255) / 256, 1024)), dim3(256), 0,
+                     s, state, (int64_t)n_seqs);
+  if (n_seeds > 0)
+    hipLaunchKernelGGL(xd_mark_kernel, dim3((n_seeds + 255) / 256), dim3(256),
+                       0, s, seeds, n_seeds, n_seqs, state);
   hipLaunchKernelGGL(xd_validate_kernel, dim3(grid), dim3(256), 0, s, seqs,
-                     offsets, n_seqs, asize, bad);
+                     offsets, n_seqs, asize, state);
   return hipGetLastError();
 }
 

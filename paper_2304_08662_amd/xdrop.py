@@ -81,11 +81,13 @@ class Request(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32),
-                ("worker_waves", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("streams", ctypes.c_int32),
+                ("arena_mib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 EXPORTS = ["xdrop_ctx_create", "xdrop_ctx_destroy", "xdrop_extend_batch",
+           "xdrop_ctx_set_timing", "xdrop_last_timing",
            "xdrop_autotune", "xdrop_load_tuning", "xdrop_extend_batch_graph",
            "xdrop_last_stats", "xdrop_server_create", "xdrop_server_submit",
            "xdrop_server_poll", "xdrop_server_wait", "xdrop_server_destroy",
@@ -117,9 +119,9 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.c_char_p, ctypes.POINTER(Options)]
     lib.xdrop_load_tuning.argtypes = [vp, ctypes.c_char_p]
     lib.xdrop_last_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
-    if not hasattr(lib, "xdrop_server_create"):
-        _lib = lib
-        return lib
+    lib.xdrop_ctx_set_timing.argtypes = [vp, i32]
+    lib.xdrop_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32,
+                                      ctypes.POINTER(ctypes.c_int32)]
     lib.xdrop_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t,
                                         ctypes.POINTER(ServerOpts),
                                         ctypes.POINTER(vp)]
@@ -130,7 +132,7 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.c_int64]
     lib.xdrop_server_destroy.argtypes = [vp]
     for f in EXPORTS:
-        if f != "xdrop_strerror" and hasattr(lib, f):
+        if f != "xdrop_strerror":
             getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -241,6 +243,21 @@ class Context:
         _check(self.lib.xdrop_load_tuning(self.handle, cache_path.encode()),
                "xdrop_load_tuning")
 
+    def set_timing(self, on: bool = True):
+        _check(self.lib.xdrop_ctx_set_timing(self.handle, int(on)),
+               "xdrop_ctx_set_timing")
+
+    def last_timing(self):
+        """Per-phase ms summed over the batches recorded since the last read
+        (prep, wave 1..8, wave 16, workgroup tier, combine) and their
+        number."""
+        arr = (ctypes.c_float * 5)()
+        nb = ctypes.c_int32()
+        _check(self.lib.xdrop_last_timing(self.handle, arr, 5,
+                                          ctypes.byref(nb)),
+               "xdrop_last_timing")
+        return list(arr), int(nb.value)
+
     def last_stats(self) -> list:
         arr = (ctypes.c_int64 * 6)()
         _check(self.lib.xdrop_last_stats(self.handle, arr, 6),
@@ -252,10 +269,10 @@ class Server:
     """Continuous-batching server (host API of include/xdrop.h)."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 64 << 30,
-                 max_inflight: int = 0, worker_waves: int = 0):
+                 max_inflight: int = 0, streams: int = 0, arena_mib: int = 0):
         self.lib = load_library()
         h = ctypes.c_void_p()
-        so = ServerOpts(max_inflight, worker_waves)
+        so = ServerOpts(max_inflight, streams, arena_mib)
         _check(self.lib.xdrop_server_create(device, budget_bytes,
                                             ctypes.byref(so), ctypes.byref(h)),
                "xdrop_server_create")
