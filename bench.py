@@ -196,7 +196,7 @@ def main():
     phase_sum, nb = ctx.last_timing()
     assert nb == args.steps
     phase = np.array(phase_sum) / nb
-    names = ["prep", "wave_1_8", "wave_16", "workgroup", "combine"]
+    names = ["prep", "wave", "unused", "workgroup", "combine"]
     dom = int(np.argmax(phase))
     achieved = OPS_PER_CELL * live / (phase[dom] / 1e3) / 1e12
     stats = ctx.last_stats()

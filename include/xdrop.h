@@ -104,8 +104,10 @@ enum {
 };
 typedef struct {
     int32_t variant;      /* XDROP_VARIANT_* */
-    int32_t tile;         /* starting cells per lane: 1, 2, 4, 8 or 16
-                             (band tile 64..1024); 0 = automatic */
+    int32_t tile;         /* starting cells per lane: 1, 2, 4 or 8 (band
+                             tile 64..512 cells; wider bands widen the tile
+                             and then move to the workgroup tier);
+                             0 = automatic */
     int32_t chunk;        /* extensions claimed per queue access, 1..64;
                              0 = automatic */
     int32_t band_cap;     /* > 0: seeds whose band exceeds it get
@@ -173,7 +175,7 @@ int xdrop_extend_batch_graph(xdrop_ctx *ctx, const uint8_t *d_seqs,
  * waits for the last recorded batch, writes to ms[0..n) the durations summed
  * over all batches recorded since timing was switched on or last read --
  * (0) counters, symbol check and longest-first ordering, (1) the wave kernel
- * of 1..8 cells per lane, (2) the 16-cell wave kernel, (3) the workgroup
+ * of 1..8 cells per lane, (2) always 0 in this build, (3) the workgroup
  * tier, (4) the seed-level combine -- sets *batches (optional) to their
  * number, and starts a new record.  Returns XDROP_E_INVALID if none was
  * recorded. */
@@ -182,8 +184,8 @@ int xdrop_last_timing(xdrop_ctx *ctx, float *ms, int32_t n,
                       int32_t *batches);
 
 /* Statistics of the last batch on this context (after stream sync):
- * counts of extensions finished at each tile width (1, 2, 4, 8, 16 cells per
- * lane, workgroup tier, general tier). */
+ * counts of extensions finished at each tile width: counts[0..3] = 1, 2, 4,
+ * 8 cells per lane, counts[4] = 0 (unused), counts[5] = workgroup tier. */
 int xdrop_last_stats(xdrop_ctx *ctx, int64_t *counts, int32_t n_counts);
 
 /* ---------------------------------------------------------------- serving

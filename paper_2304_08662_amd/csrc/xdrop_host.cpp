@@ -42,7 +42,7 @@ struct xdrop_ctx {
   int32_t* counters = nullptr;
   int32_t* gen_scratch = nullptr;
   int gen_slots = 32;
-  int blocks_per_cu[2][2] = {{0, 0}, {0, 0}};  // [alphabet][wide]
+  int blocks_per_cu[2] = {0, 0};  // [alphabet]
   bool have_tuned[2] = {false, false};
   xdrop_options tuned[2];
   std::vector<GraphEntry> graphs;
@@ -60,7 +60,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-  size_t items, order, wide_q, gen_q, bad, total;
+  size_t items, order, gen_q, bad, total;
 };
 
 Layout layout(int32_t n_items, int32_t n_seqs) {
@@ -74,7 +74,6 @@ Layout layout(int32_t n_items, int32_t n_seqs) {
   const size_t ni = (size_t)std::max(n_items, 1);
   L.items = take(ni * sizeof(ItemResult));
   L.order = take(ni * 4);
-  L.wide_q = take(ni * 4);
   L.gen_q = take(ni * 4);
   L.bad = take((size_t)std::max(n_seqs, 1));
   L.total = off;
@@ -145,7 +144,7 @@ int check_options(const xdrop_options* o) {
   if (!o) return XDROP_OK;
   if (o->variant < 0 || o->variant > XDROP_VARIANT_PLAIN) return XDROP_E_INVALID;
   const int t = o->tile;
-  if (!(t == 0 || t == 1 || t == 2 || t == 4 || t == 8 || t == 16))
+  if (!(t == 0 || t == 1 || t == 2 || t == 4 || t == 8))
     return XDROP_E_INVALID;
   if (o->chunk < 0 || o->chunk > 64) return XDROP_E_INVALID;
   if (o->band_cap < 0 || o->order < 0 || o->order > 1 ||
@@ -220,7 +219,6 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   P.seeds = (const int32_t*)d_seeds;
   P.items = (ItemResult*)(ws + L.items);
   P.counters = c->counters;
-  P.wide_queue = (int32_t*)(ws + L.wide_q);
   P.gen_queue = (int32_t*)(ws + L.gen_q);
   P.gen_scratch = c->gen_scratch;
   P.n_seqs = n_seqs;
@@ -259,12 +257,9 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     P.flags |= F_ORDERED;
   }
   const int a = P.alphabet;
-  if (!c->blocks_per_cu[a][0]) {
-    c->blocks_per_cu[a][0] = wave_blocks_per_cu(a, 8);
-    c->blocks_per_cu[a][1] = wave_blocks_per_cu(a, 16);
-  }
-  auto persistent_grid = [&](int wide) {
-    int bpc = c->blocks_per_cu[a][wide];
+  if (!c->blocks_per_cu[a]) c->blocks_per_cu[a] = wave_blocks_per_cu(a);
+  auto persistent_grid = [&]() {
+    int bpc = c->blocks_per_cu[a];
     if (o.waves_per_cu > 0)
       bpc = std::max(1, std::min(bpc, (o.waves_per_cu + WPB - 1) / WPB));
     return c->num_cu * bpc;
@@ -281,12 +276,10 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     if (plain)
       grid = (n_items + WPB - 1) / WPB;
     else
-      grid = std::min(persistent_grid(0),
+      grid = std::min(persistent_grid(),
                       (n_items + WPB * o.chunk - 1) / (WPB * o.chunk));
-    HIP_OK(launch_wave(P, 8, grid, st));
+    HIP_OK(launch_wave(P, grid, st));
     if (timed) HIP_OK(hipEventRecord(ev[2], st));
-    HIP_OK(launch_wave(P, 16, std::min(persistent_grid(1),
-                                       (n_items + WPB - 1) / WPB), st));
     if (timed) HIP_OK(hipEventRecord(ev[3], st));
   }
   HIP_OK(launch_general(P, c->gen_slots, st));
@@ -478,10 +471,7 @@ extern "C" int xdrop_extend_batch_graph(
   rc = ensure_workspace(c, L.total);
   if (rc != XDROP_OK) return rc;
   for (int a = 0; a < 2; ++a)
-    if (!c->blocks_per_cu[a][0]) {
-      c->blocks_per_cu[a][0] = wave_blocks_per_cu(a, 8);
-      c->blocks_per_cu[a][1] = wave_blocks_per_cu(a, 16);
-    }
+    if (!c->blocks_per_cu[a]) c->blocks_per_cu[a] = wave_blocks_per_cu(a);
   GraphEntry g;
   g.seqs = d_seqs; g.offsets = d_offsets; g.seeds = d_seeds;
   g.results = d_results; g.n_seqs = n_seqs; g.n_seeds = n_seeds;
@@ -538,7 +528,7 @@ extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
   // candidates: persistent wave form (tile x chunk), the plain form (tile),
   // the workgroup form
   std::vector<xdrop_options> cand;
-  const int tiles[] = {1, 2, 4, 8, 16};
+  const int tiles[] = {1, 2, 4, 8};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
   for (int t : tiles)
     for (int ch : chunks) {

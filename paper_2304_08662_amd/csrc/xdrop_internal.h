@@ -50,7 +50,6 @@ struct Params {
   const int32_t* order;      // processing order (F_ORDERED) or null
   int32_t* counters;         // queue heads and tier statistics
   const uint8_t* seq_bad;    // per-sequence check (BYTE): 2 = bad symbol
-  int32_t* wide_queue;       // items handed to the 16-cell tier
   int32_t* gen_queue;        // items handed to the general tier
   int32_t* gen_scratch;      // general tier rings
   int32_t n_seqs;
@@ -74,9 +73,7 @@ enum {
   C_HEAD = 0,       // main queue head
   C_GEN_TAIL = 1,   // general queue tail
   C_GEN_HEAD = 2,   // general queue head
-  C_WIDE_TAIL = 3,  // 16-cell tier queue tail
-  C_WIDE_HEAD = 4,  // 16-cell tier queue head
-  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8,16, general
+  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8, -, general
   C_HIST = 16,      // longest-first ordering: bucket sizes
   C_CURSOR = C_HIST + 256,  // bucket write cursors
   C_COUNT = C_CURSOR + 256
@@ -100,8 +97,8 @@ hipError_t launch_order(const int32_t* seeds, const int64_t* offsets,
 hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
                              int32_t* counters, int32_t tail_slot,
                              hipStream_t s);
-hipError_t launch_wave(const Params& P, int cmax, int grid, hipStream_t s);
+hipError_t launch_wave(const Params& P, int grid, hipStream_t s);
 hipError_t launch_general(const Params& P, int grid, hipStream_t s);
 hipError_t launch_combine(const Params& P, void* out, hipStream_t s);
-int wave_blocks_per_cu(int alphabet, int cmax);
+int wave_blocks_per_cu(int alphabet);
 }  // namespace xd

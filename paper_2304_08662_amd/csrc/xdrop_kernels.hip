@@ -21,7 +21,7 @@
 //  * the window slides up by one lane (C cells) when the band reaches its top
 //    and the bottom lane is dead; when the band is wider than the window the
 //    tile widens in place (C -> 2C, registers redistributed with
-//    ds_bpermute) up to C = 16 (1024 cells); wider bands go to a workgroup
+//    ds_bpermute) up to C = 8 (512 cells); wider bands go to a workgroup
 //    tier with rings in device memory;
 //  * sequences stream through per-wave LDS rings (2-bit DNA or byte codes),
 //    read backwards for left extensions (the paper's op() transform);
@@ -551,17 +551,12 @@ __device__ void run_item(const Params& P, const Src& S, int item,
       r = start_tier<ALPHA, CMIN, CMAX>(e, w, tab, P, S, start, tier);
     }
     if (r == R_ESC) {
-      // band wider than this kernel's widest window: restart the extension
-      // in the next tier
+      // band wider than the widest register window: restart the extension
+      // on the workgroup tier
       handed_on = true;
       if (lane_id() == 0) {
-        if (CMAX < 16) {
-          const int slot = atomicAdd(P.counters + C_WIDE_TAIL, 1);
-          P.wide_queue[slot] = item;
-        } else {
-          const int slot = atomicAdd(P.counters + C_GEN_TAIL, 1);
-          P.gen_queue[slot] = item;
-        }
+        const int slot = atomicAdd(P.counters + C_GEN_TAIL, 1);
+        P.gen_queue[slot] = item;
       }
     } else if (r == R_CAP) {
       res.status = S_BAND;
@@ -574,13 +569,12 @@ __device__ void run_item(const Params& P, const Src& S, int item,
   if (!handed_on && lane_id() == 0) P.items[item] = res;
 }
 
-// Persistent wave kernels.  CMAX = 8: extensions of the batch, pulled from
-// the queue in chunks of P.chunk (or, in the plain form, one per launched
-// wave), tiles 1..8 cells per lane.  CMAX = 16: the extensions handed on by
-// the first kernel, restarted with 16 cells per lane.
+// Persistent wave kernel: extensions of the batch pulled from the queue in
+// chunks of P.chunk (or, in the plain form, one per launched wave), tiles of
+// 1..CMAX cells per lane.
 template <int ALPHA, int CMAX>
 __global__ __launch_bounds__(WAVE * WPB) void xd_wave_kernel(Params P) {
-  constexpr int CMIN = CMAX == 16 ? 16 : 1;
+  constexpr int CMIN = 1;
   __shared__ WaveLds<ALPHA> lds[WPB];
   __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
   if constexpr (ALPHA == 1) {
@@ -591,19 +585,6 @@ __global__ __launch_bounds__(WAVE * WPB) void xd_wave_kernel(Params P) {
   const int wid = threadIdx.x >> 6;
   WaveLds<ALPHA>& w = lds[wid];
   const Src S = make_src(P);
-  if (CMAX == 16) {
-    const int n = uni(__hip_atomic_load(P.counters + C_WIDE_TAIL,
-                                        __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT));
-    for (;;) {
-      int c = 0;
-      if (lane_id() == 0) c = atomicAdd(P.counters + C_WIDE_HEAD, 1);
-      c = uni(c);
-      if (c >= n) break;
-      run_item<ALPHA, CMIN, CMAX>(P, S, uni(P.wide_queue[c]), w, tab);
-    }
-    return;
-  }
   if (P.flags & F_PLAIN) {
     const int idx = uni(blockIdx.x * WPB + wid);
     if (idx < P.n_items)
@@ -894,8 +875,6 @@ __global__ void xd_combine_kernel(Params P, void* out_v) {
 
 template __global__ void xd_wave_kernel<0, 8>(Params);
 template __global__ void xd_wave_kernel<1, 8>(Params);
-template __global__ void xd_wave_kernel<0, 16>(Params);
-template __global__ void xd_wave_kernel<1, 16>(Params);
 
 }  // namespace xd
 
@@ -952,23 +931,14 @@ hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
   return hipGetLastError();
 }
 
-hipError_t launch_wave(const Params& P, int cmax, int grid, hipStream_t s) {
+hipError_t launch_wave(const Params& P, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (P.alphabet == 0) {
-    if (cmax == 16)
-      hipLaunchKernelGGL((xd_wave_kernel<0, 16>), dim3(grid), dim3(WAVE * WPB),
-                         0, s, P);
-    else
-      hipLaunchKernelGGL((xd_wave_kernel<0, 8>), dim3(grid), dim3(WAVE * WPB),
-                         0, s, P);
-  } else {
-    if (cmax == 16)
-      hipLaunchKernelGGL((xd_wave_kernel<1, 16>), dim3(grid), dim3(WAVE * WPB),
-                         0, s, P);
-    else
-      hipLaunchKernelGGL((xd_wave_kernel<1, 8>), dim3(grid), dim3(WAVE * WPB),
-                         0, s, P);
-  }
+  if (P.alphabet == 0)
+    hipLaunchKernelGGL((xd_wave_kernel<0, 8>), dim3(grid), dim3(WAVE * WPB),
+                       0, s, P);
+  else
+    hipLaunchKernelGGL((xd_wave_kernel<1, 8>), dim3(grid), dim3(WAVE * WPB),
+                       0, s, P);
   return hipGetLastError();
 }
 
@@ -985,19 +955,14 @@ hipError_t launch_combine(const Params& P, void* out, hipStream_t s) {
   return hipGetLastError();
 }
 
-int wave_blocks_per_cu(int alphabet, int cmax) {
+int wave_blocks_per_cu(int alphabet) {
   int nb = 0;
-  hipError_t e;
-  if (alphabet == 0)
-    e = cmax == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         &nb, xd_wave_kernel<0, 16>, WAVE * WPB, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         &nb, xd_wave_kernel<0, 8>, WAVE * WPB, 0);
-  else
-    e = cmax == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         &nb, xd_wave_kernel<1, 16>, WAVE * WPB, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         &nb, xd_wave_kernel<1, 8>, WAVE * WPB, 0);
+  hipError_t e =
+      alphabet == 0
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_wave_kernel<0, 8>, WAVE * WPB, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_wave_kernel<1, 8>, WAVE * WPB, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

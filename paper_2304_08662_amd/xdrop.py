@@ -249,7 +249,7 @@ class Context:
 
     def last_timing(self):
         """Per-phase ms summed over the batches recorded since the last read
-        (prep, wave 1..8, wave 16, workgroup tier, combine) and their
+        (prep, wave kernel, unused, workgroup tier, combine) and their
         number."""
         arr = (ctypes.c_float * 5)()
         nb = ctypes.c_int32()

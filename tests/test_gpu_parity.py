@@ -117,9 +117,10 @@ def test_small_alphabet_bytes(runner):
     assert not compare(g, ref)
 
 
-HANG_REASON = ("skipped: a GPU run of this case did not finish; the cause is "
-               "not yet shown (the CPU emulation of the same kernels is "
-               "bit-exact on the same batch)")
+HANG_REASON = ("skipped: a GPU run of this case (with the since removed "
+               "16-cell wave kernel) did not finish and the cause is not "
+               "shown; the case stays off the GPU (the CPU emulation of the "
+               "same kernels is bit-exact on the same batch)")
 
 
 @pytest.mark.parametrize("name,scale", [
@@ -141,7 +142,6 @@ def test_variants_identical(runner):
     scheme = inputs.Scheme(4, 1, -1, -1, 40)
     ref = oracle_run(batch, scheme)
     dev = runner.upload(batch)
-    # tile 16 (the 16-cell kernel) is left out while HANG_REASON stands
     for v, tile, chunk, order in [(1, 1, 1, 0), (1, 2, 3, 0), (1, 4, 8, 1),
                                   (1, 8, 64, 0), (3, 1, 1, 0), (3, 8, 1, 1),
                                   (2, 1, 1, 0)]:
@@ -151,10 +151,9 @@ def test_variants_identical(runner):
         assert not bad, ((v, tile, chunk, order), bad[:5])
 
 
-@pytest.mark.skip(reason=HANG_REASON)
 def test_wide_bands_all_tiers(runner):
     # X -> infinity on unrelated pairs: bands up to min(m, n), crossing the
-    # 64..1024 register tiles and the workgroup tier
+    # 64..512 register tiles and the workgroup tier
     rng = np.random.default_rng(24)
     pairs = []
     for L in (40, 130, 300, 600, 1100, 1500):
@@ -167,7 +166,7 @@ def test_wide_bands_all_tiers(runner):
     g = runner.run(batch, scheme)
     assert not compare(g, ref)
     stats = runner.ctx.last_stats()
-    assert stats[4] >= 1 and stats[5] >= 1, stats
+    assert stats[3] >= 1 and stats[5] >= 1, stats
 
 
 def test_statuses(runner):
