@@ -14,6 +14,10 @@ constexpr int32_t THR_FLOOR = -(1 << 29);
 constexpr int64_t VALUE_LIMIT = int64_t(1) << 28;
 constexpr int32_t X_CLAMP = 1 << 30;  // X >= 2^30 acts as infinity
 constexpr int32_t MAX_ENTRY = 1024;   // |matrix entry|, |gap| bound
+// Finite range [L, U] of an antidiagonal with no finite cell: L > U, and the
+// pair drops out of every min(L..) / max(U..) of band bounds.
+constexpr int32_t DEAD_L = 1 << 30;
+constexpr int32_t DEAD_U = -(1 << 30);
 
 constexpr int WAVE = 64;
 constexpr int WPB = 4;                // waves per block of the wave kernels

@@ -69,6 +69,18 @@ __device__ __forceinline__ int uni(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Minimum / maximum of wave-uniform values.  The readfirstlane keeps the
+// compiler from fusing nested uniform min/max into VALU min3/max3, whose
+// results would pull the whole scalar state of the sweep into VGPRs.
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)uni((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)uni((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int smin(int a, int b) { return uni(min(a, b)); }
+__device__ __forceinline__ int smax(int a, int b) { return uni(max(a, b)); }
+
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo,
                                            uint32_t sh) {
   return __builtin_amdgcn_alignbit(hi, lo, sh);
@@ -209,11 +221,33 @@ struct Ext {
   int d;              // next antidiagonal to compute
   int base;           // window position 0 is x = base
   int T, bx, by;      // best score (S frame) and its cell
-  int L1, U1, alive1; // finite range of d-1
-  int L2, U2, alive2; // finite range of d-2
+  int L1, U1;         // finite range of d-1 (L1 > U1: no finite cell)
+  int L2, U2;         // finite range of d-2
   int64_t W;          // live-span cells so far
   int loaded_a, loaded_b;  // ring fill levels (elements)
+  // queue of the target codes that enter the window at lane 0, one per
+  // antidiagonal: b[qi], b[qi+1], ... with the next code in the low bits
+  uint64_t q;
+  int qn;             // codes left in q
+  int qi;             // element index of the next code
 };
+
+// Keep the scalar state in SGPRs: every field is the same in all lanes.
+__device__ __forceinline__ void make_uniform(Ext& e) {
+  e.d = uni(e.d);
+  e.base = uni(e.base);
+  e.T = uni(e.T);
+  e.bx = uni(e.bx);
+  e.by = uni(e.by);
+  e.L1 = uni(e.L1);
+  e.U1 = uni(e.U1);
+  e.L2 = uni(e.L2);
+  e.U2 = uni(e.U2);
+  e.loaded_a = uni(e.loaded_a);
+  e.loaded_b = uni(e.loaded_b);
+  e.qn = uni(e.qn);
+  e.qi = uni(e.qi);
+}
 
 enum { R_CONT = 0, R_DONE = 1, R_ESC = 2, R_CAP = 3 };
 
@@ -223,37 +257,10 @@ struct WaveLds {
   uint32_t rb[Ring<ALPHA>::WORDS];
 };
 
-// Query-side symbols of a lane's C cells (depend only on base and C).
-template <int ALPHA, int C>
-struct ASyms;
-
-template <int C>
-struct ASyms<0, C> {
-  uint32_t f;  // cell j at 2-bit field C-1-j
-  __device__ void load(const WaveLds<0>& w, int base) {
-    uint32_t v = Ring<0>::read(w.ra, base + lane_id() * C - 1);
-    f = rev2(v) >> (32 - 2 * C);
-  }
-};
-
-template <int C>
-struct ASyms<1, C> {
-  int row[C];  // 32 * code of cell j's query symbol
-  __device__ void load(const WaveLds<1>& w, int base) {
-    constexpr int NW = (C + 3) / 4;
-    uint32_t v[NW];
-    Ring<1>::read<NW>(w.ra, base + lane_id() * C - 1, v);
-#pragma unroll
-    for (int j = 0; j < C; ++j)
-      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) << 5;
-  }
-};
-
 template <int ALPHA>
 __device__ __forceinline__ void cover_a(Ext& e, WaveLds<ALPHA>& w,
                                         const Src& P, int need_hi) {
-  // make element need_hi (and everything below it down to the window)
-  // available
+  // make elements up to need_hi available (the ring keeps the RS below)
   while (e.loaded_a <= need_hi) {
     Ring<ALPHA>::fill(w.ra, P, e.a_start, e.a_dir, e.loaded_a);
     e.loaded_a += Ring<ALPHA>::CH;
@@ -271,152 +278,244 @@ __device__ __forceinline__ void cover_b(Ext& e, WaveLds<ALPHA>& w,
   __builtin_amdgcn_wave_barrier();
 }
 
-// ------------------------------------------------------------------ step
-// Computes antidiagonal e.d into `cur` (which holds d-2 on entry) from
-// `prev` (d-1).  On R_CONT the caller swaps the roles of the two arrays.
+// Symbols of a lane's C cells.  Query codes (A) depend only on the window
+// (base, C) and are read from the ring when it moves; target codes (B) move
+// by one cell per antidiagonal: cell j takes cell j-1's code, cell 0 takes
+// cell C-1 of the lane below, and lane 0 takes the next code of the queue.
+// DNA: 2-bit codes, cell j at bits [30-2j, 32-2j) of one word.
+// Bytes: cell j at byte 4*NB-1-j of NB words (cell 0 in the top byte);
+// the query side keeps 32 * code per cell (row offset of the score table).
 template <int ALPHA, int C>
-__device__ __forceinline__ int step(Ext& e, int (&prev)[C], int (&cur)[C],
-                                    ASyms<ALPHA, C>& as, WaveLds<ALPHA>& w,
+struct Syms;
+
+template <int C>
+struct Syms<0, C> {
+  static constexpr int QBITS = 2, QCODES = 16;
+  uint32_t a, b;
+  __device__ void load_a(const WaveLds<0>& w, int base) {
+    a = rev2(Ring<0>::read(w.ra, base + lane_id() * C - 1));
+  }
+  __device__ void load_b(const WaveLds<0>& w, int d, int base) {
+    const int yb = d - base - lane_id() * C - 1;
+    b = Ring<0>::read(w.rb, yb - C + 1) << (32 - 2 * C);
+  }
+  // codes of the next antidiagonal; `in` = the code entering at lane 0
+  __device__ void advance(uint32_t in) {
+    const uint32_t below = (uint32_t)wave_shr1((int)b, (int)(in << (32 - 2 * C)));
+    b = funnel(below >> (32 - 2 * C), b, 2);
+  }
+  __device__ int sim(int j, const Params& P, const int*) const {
+    return (((a ^ b) >> (30 - 2 * j)) & 3u) ? P.mis_s : P.mat_s;
+  }
+  // 16 codes from element e0 (next code lowest)
+  __device__ static uint64_t queue(const WaveLds<0>& w, int e0) {
+    return (uint64_t)(uint32_t)uni((int)Ring<0>::read(w.rb, e0));
+  }
+};
+
+template <int C>
+struct Syms<1, C> {
+  static constexpr int QBITS = 8, QCODES = 8;
+  static constexpr int NB = (C + 3) / 4;
+  int row[C];
+  uint32_t b[NB];
+  __device__ void load_a(const WaveLds<1>& w, int base) {
+    uint32_t v[NB];
+    Ring<1>::read<NB>(w.ra, base + lane_id() * C - 1, v);
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) << 5;
+  }
+  __device__ void load_b(const WaveLds<1>& w, int d, int base) {
+    const int yb = d - base - lane_id() * C - 1;
+    Ring<1>::read<NB>(w.rb, yb - C + 1, b);
+    if constexpr (C < 4) b[0] <<= 8 * (4 - C);
+  }
+  __device__ void advance(uint32_t in) {
+    if constexpr (NB == 1) {
+      const uint32_t below =
+          (uint32_t)wave_shr1((int)b[0], (int)(in << (8 * (4 - C))));
+      b[0] = funnel(below >> (8 * (4 - C)), b[0], 8);
+    } else {
+      const uint32_t below = (uint32_t)wave_shr1((int)b[0], (int)in);
+#pragma unroll
+      for (int k = 0; k < NB - 1; ++k) b[k] = funnel(b[k + 1], b[k], 8);
+      b[NB - 1] = funnel(below, b[NB - 1], 8);
+    }
+  }
+  __device__ int sim(int j, const Params&, const int* tab) const {
+    constexpr int NBY = 4 * NB;
+    const int k = NBY - 1 - j;  // byte index of cell j
+    const int code = (int)((b[k >> 2] >> (8 * (k & 3))) & 31u);
+    return tab[row[j] + code];
+  }
+  // 8 codes from element e0 (next code lowest)
+  __device__ static uint64_t queue(const WaveLds<1>& w, int e0) {
+    uint32_t v[2];
+    Ring<1>::read<2>(w.rb, e0, v);
+    return ((uint64_t)(uint32_t)uni((int)v[1]) << 32) |
+           (uint32_t)uni((int)v[0]);
+  }
+};
+
+// Window contents after the window or the tile changed: query codes, target
+// codes of antidiagonal e.d, and an empty code queue.
+template <int ALPHA, int C>
+__device__ __forceinline__ void reload_syms(Ext& e, Syms<ALPHA, C>& sy,
+                                            WaveLds<ALPHA>& w, const Src& S) {
+  cover_a<ALPHA>(e, w, S, e.base + 64 * C - 2);
+  cover_b<ALPHA>(e, w, S, e.d - e.base - 1);
+  sy.load_a(w, e.base);
+  sy.load_b(w, e.d, e.base);
+  e.qi = e.d - e.base;  // code entering lane 0 for antidiagonal e.d + 1
+  e.qn = 0;
+}
+
+// ------------------------------------------------------------------ step
+// Computes antidiagonal e.d.  On entry A holds d-1 and B holds d-2; on exit
+// A holds d and B holds d-1.  The body is straight-line code with three
+// rarely taken uniform branches (a new best score, a window move, a refill
+// of the target-code queue) and one exit value, so that the compiler keeps
+// the sweep state in SGPRs.
+template <int ALPHA, int C>
+__device__ __forceinline__ int step(Ext& e, int (&A)[C], int (&B)[C],
+                                    Syms<ALPHA, C>& sy, WaveLds<ALPHA>& w,
                                     const int* tab, const Params& P,
                                     const Src& S) {
+  constexpr int LOG2C = C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : 3;
   const int lane = lane_id();
   const int d = e.d;
 
-  // span of this antidiagonal (live-span count, band cap)
-  {
-    int lo = 0x7fffffff, hi = -0x7fffffff;
-    if (e.alive1) { lo = min(lo, e.L1); hi = max(hi, e.U1 + 1); }
-    if (e.alive2) { lo = min(lo, e.L2 + 1); hi = max(hi, e.U2 + 1); }
-    lo = max(lo, max(0, d - e.n));
-    hi = min(hi, min(e.m, d));
-    if (hi >= lo) {
-      e.W += hi - lo + 1;
-      if (P.band_cap > 0 && hi - lo + 1 > P.band_cap) return R_CAP;
-    }
-  }
-
-  // target-side symbols of this step: cell j of lane l has b element
-  // d - base - l*C - 1 - j
-  cover_b<ALPHA>(e, w, S, d - e.base - 1);
-  const int yb = d - e.base - lane * C - 1;
-
-  int s[C];
-  if constexpr (ALPHA == 0) {
-    uint32_t bf = Ring<0>::read(w.rb, yb - C + 1);  // cell j at field C-1-j
-    uint32_t x = bf ^ as.f;
-#pragma unroll
-    for (int j = 0; j < C; ++j)
-      s[j] = ((x >> (2 * (C - 1 - j))) & 3u) ? P.mis_s : P.mat_s;
-  } else {
-    constexpr int NW = (C + 3) / 4;
-    uint32_t bw[NW];
-    Ring<1>::read<NW>(w.rb, yb - C + 1, bw);  // cell j at byte C-1-j
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int k = C - 1 - j;
-      int bc = (int)((bw[k >> 2] >> (8 * (k & 3))) & 31u);
-      s[j] = tab[as.row[j] + bc];
-    }
-  }
+  // span of this antidiagonal (live-span count, band cap); an empty range
+  // (DEAD_L, DEAD_U) drops out of the min / max
+  const int lo = smax(smin(e.L1, e.L2 + 1), smax(0, d - e.n));
+  const int hi = smin(smax(e.U1, e.U2) + 1, smin(e.m, d));
+  const int width = hi - lo + 1;
+  if (width > 0) e.W += width;
+  const bool cap_hit = P.band_cap > 0 && width > P.band_cap;
 
   // neighbours from the lane below (window position l*C - 1)
-  const int up0 = wave_shr1(prev[C - 1], NEG);
-  const int dg0 = wave_shr1(cur[C - 1], NEG);
+  const int up0 = wave_shr1(A[C - 1], NEG);
+  const int dg0 = wave_shr1(B[C - 1], NEG);
 
-  // thresholds in the V frame: S >= T - X  <=>  V >= T - X - gap*d
-  int thr = e.T - P.X - P.gap * d;
-  thr = max(thr, THR_FLOOR);
-  const int pmin = d - e.n - e.base;  // positions below: y > n
-  const int pmax = e.m - e.base;      // positions above: x > m
-  const bool edge = (pmin > 0) | (pmax < 64 * C - 1);
+  // prune threshold in the V frame: S >= T - X  <=>  V >= T - X - gap*d
+  const int thr = smax(e.T - P.X - P.gap * d, THR_FLOOR);
+  // window positions p with y > n (p < pmin) or x > m (p > pmin + span)
+  // are outside the matrix
+  const int pmin = d - e.n - e.base;
+  const uint32_t span = (uint32_t)(e.m - e.base - pmin);
 
   int v[C];
 #pragma unroll
   for (int j = C - 1; j >= 0; --j) {
-    const int up = j ? prev[j - 1] : up0;
-    const int dg = j ? cur[j - 1] : dg0;
-    v[j] = max(max(up, prev[j]), dg + s[j]);
-  }
-  if (edge) {
-    const int p0 = lane * C;
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int p = p0 + j;
-      if (p < pmin || p > pmax) v[j] = NEG;
-    }
+    const int up = j ? A[j - 1] : up0;
+    const int dg = j ? B[j - 1] : dg0;
+    v[j] = max(max(up, A[j]), dg + sy.sim(j, P, tab));
   }
   uint64_t msk[C];
   uint64_t any = 0;
   int lm = NEG;
 #pragma unroll
   for (int j = 0; j < C; ++j) {
-    const bool f = v[j] >= thr;
-    cur[j] = f ? v[j] : NEG;
+    const bool f = v[j] >= thr && (uint32_t)(lane * C + j - pmin) <= span;
+    v[j] = f ? v[j] : NEG;
     msk[j] = ballot(f);
     any |= msk[j];
-    lm = max(lm, cur[j]);
+    lm = max(lm, v[j]);
   }
-
-  // running best (S frame value T <=> V frame value T - gap*d)
-  const int Tv = e.T - P.gap * d;
-  if (ballot(lm > Tv)) {
-    const int wm = wave_max(lm);
-    const uint64_t eq = ballot(lm == wm);
-    const int l0 = __builtin_ctzll(eq);
-    int jf = C - 1;
 #pragma unroll
-    for (int j = C - 1; j >= 0; --j)
-      if (cur[j] == wm) jf = j;
-    const int js = __builtin_amdgcn_readlane(jf, l0);
+  for (int j = 0; j < C; ++j) { B[j] = A[j]; A[j] = v[j]; }
+
+  // running best (S frame value T <=> V frame value T - gap*d); the wave
+  // maximum is needed only when some lane beats T, and is one readlane when
+  // a single lane does
+  const int Tv = e.T - P.gap * d;
+  const uint64_t imp = ballot(lm > Tv);
+  if (imp) {
+    int wm, l0;
+    if (__builtin_popcountll(imp) == 1) {
+      l0 = __builtin_ctzll(imp);
+      wm = __builtin_amdgcn_readlane(lm, l0);
+    } else {
+      wm = uni(wave_max(lm));
+      l0 = __builtin_ctzll(ballot(lm == wm));
+    }
+    int js = 0;
+    if constexpr (C > 1) {
+      int jf = C - 1;
+#pragma unroll
+      for (int j = C - 1; j >= 0; --j)
+        if (A[j] == wm) jf = j;
+      js = __builtin_amdgcn_readlane(jf, l0);
+    }
     e.T = wm + P.gap * d;
     e.bx = e.base + l0 * C + js;
     e.by = d - e.bx;
   }
 
   // finite range of d
-  int alive0 = any != 0, L0 = 0, U0 = 0;
-  if (alive0) {
+  int L0 = DEAD_L, U0 = DEAD_U;
+  if (any) {
     const int llo = __builtin_ctzll(any);
     const int lhi = 63 - __builtin_clzll(any);
     int jlo = 0, jhi = 0;
+    if constexpr (C > 1) {
 #pragma unroll
-    for (int j = C - 1; j >= 0; --j)
-      if ((msk[j] >> llo) & 1) jlo = j;
+      for (int j = C - 1; j >= 0; --j)
+        if ((msk[j] >> llo) & 1) jlo = j;
 #pragma unroll
-    for (int j = 0; j < C; ++j)
-      if ((msk[j] >> lhi) & 1) jhi = j;
-    L0 = e.base + llo * C + jlo;
-    U0 = e.base + lhi * C + jhi;
+      for (int j = 0; j < C; ++j)
+        if ((msk[j] >> lhi) & 1) jhi = j;
+    }
+    L0 = e.base + (llo << LOG2C) + jlo;
+    U0 = e.base + (lhi << LOG2C) + jhi;
   }
 
-  const int alive1 = e.alive1, L1 = e.L1, U1 = e.U1;
-  e.L2 = e.L1; e.U2 = e.U1; e.alive2 = e.alive1;
-  e.L1 = L0; e.U1 = U0; e.alive1 = alive0;
+  const int L1 = e.L1, U1 = e.U1;
+  e.L2 = L1; e.U2 = U1;
+  e.L1 = L0; e.U1 = U0;
   e.d = d + 1;
-  if ((!alive0 && !alive1) || d >= e.m + e.n) return R_DONE;
+  int r = R_CONT;
+  if ((!any && L1 > U1) || d >= e.m + e.n) r = R_DONE;
 
   // keep the next antidiagonal's band inside the window
-  int hi_next = -0x7fffffff;
-  if (alive0) hi_next = U0 + 1;
-  if (alive1) hi_next = max(hi_next, U1 + 1);
-  hi_next = min(hi_next, min(e.m, d + 1));
-  const int top = e.base + 64 * C - 1;
-  if (hi_next > top) {
-    int lo_fin = 0x7fffffff;
-    if (alive0) lo_fin = L0;
-    if (alive1) lo_fin = min(lo_fin, L1);
-    if (e.base + C > lo_fin) return R_ESC;
-    // slide the window up by one lane
+  const int hi_next = smin(smax(U0, U1) + 1, smin(e.m, d + 1));
+  if (r == R_CONT && hi_next > e.base + 64 * C - 1) {
+    // slide the window up by as many whole lanes as the dead cells below
+    // the band allow (cells below min(L0, L1) are -infinity on d and d-1)
+    const int sl = (smin(L0, L1) - e.base) >> LOG2C;
+    if (sl < 1) {
+      r = R_ESC;
+    } else {
+      const int src = lane + sl;
+      const bool in = src < 64;
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      cur[j] = wave_shl1(cur[j], NEG);
-      prev[j] = wave_shl1(prev[j], NEG);
+      for (int j = 0; j < C; ++j) {
+        const int pa = __builtin_amdgcn_ds_bpermute((src & 63) << 2, A[j]);
+        const int pb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, B[j]);
+        A[j] = in ? pa : NEG;
+        B[j] = in ? pb : NEG;
+      }
+      e.base += sl << LOG2C;
+      reload_syms<ALPHA, C>(e, sy, w, S);
     }
-    e.base += C;
-    cover_a<ALPHA>(e, w, S, e.base + 64 * C - 2);
-    as.load(w, e.base);
+  } else if (r == R_CONT) {
+    // target codes of the next antidiagonal: one code enters at lane 0
+    if (e.qn == 0) {
+      cover_b<ALPHA>(e, w, S, e.qi + Syms<ALPHA, C>::QCODES - 1);
+      e.q = Syms<ALPHA, C>::queue(w, e.qi);
+      e.qn = Syms<ALPHA, C>::QCODES;
+    }
+    const uint32_t in =
+        (uint32_t)(e.q & ((1u << Syms<ALPHA, C>::QBITS) - 1));
+    e.q >>= Syms<ALPHA, C>::QBITS;
+    e.qn -= 1;
+    e.qi += 1;
+    sy.advance(in);
   }
-  return R_CONT;
+  if (cap_hit) r = R_CAP;
+  make_uniform(e);
+  return r;
 }
 
 // Redistribute a window of C cells per lane into 2C cells per lane
@@ -441,23 +540,19 @@ __device__ int run_tier(Ext& e, int (&A)[C], int (&B)[C], WaveLds<ALPHA>& w,
                         const int* tab, const Params& P, const Src& S,
                         int start, int& tier_out) {
   int r = R_ESC;
-  bool newest_in_B = false;
   if (start <= C) {
-    ASyms<ALPHA, C> as;
-    cover_a<ALPHA>(e, w, S, e.base + 64 * C - 2);
-    as.load(w, e.base);
-    for (;;) {
-      r = step<ALPHA, C>(e, A, B, as, w, tab, P, S);
-      if (r != R_CONT) { newest_in_B = true; break; }
-      r = step<ALPHA, C>(e, B, A, as, w, tab, P, S);
-      if (r != R_CONT) { newest_in_B = false; break; }
-    }
+    Syms<ALPHA, C> sy;
+    reload_syms<ALPHA, C>(e, sy, w, S);
+    make_uniform(e);
+    do {
+      r = step<ALPHA, C>(e, A, B, sy, w, tab, P, S);
+    } while (r == R_CONT);
   }
   if constexpr (C < CMAX) {
     if (r == R_ESC) {
       int N1[2 * C], N2[2 * C];
-      if (newest_in_B) { widen<C>(B, N1); widen<C>(A, N2); }
-      else { widen<C>(A, N1); widen<C>(B, N2); }
+      widen<C>(A, N1);
+      widen<C>(B, N2);
       return run_tier<ALPHA, 2 * C, CMAX>(e, N1, N2, w, tab, P, S, start,
                                           tier_out);
     }
@@ -489,21 +584,24 @@ __device__ __forceinline__ ItemSetup setup_item(const Params& P, int item) {
   const int seed = item >> 1;
   const int right = item & 1;
   const int* sd = P.seeds + 5 * (int64_t)seed;
-  const int q = sd[0], t = sd[1], qp = sd[2], tp = sd[3], k = sd[4];
+  // wave-uniform loads: readfirstlane keeps them (and the state derived
+  // from them) in SGPRs
+  const int q = uni(sd[0]), t = uni(sd[1]), qp = uni(sd[2]),
+            tp = uni(sd[3]), k = uni(sd[4]);
   Ext& e = s.e;
   e.m = e.n = 0;
   if (q < 0 || q >= P.n_seqs || t < 0 || t >= P.n_seqs) {
     s.status = S_RANGE;
     return s;
   }
-  const int64_t oq = P.offsets[q], lq = P.offsets[q + 1] - oq;
-  const int64_t ot = P.offsets[t], lt = P.offsets[t + 1] - ot;
+  const int64_t oq = uni64(P.offsets[q]), lq = uni64(P.offsets[q + 1]) - oq;
+  const int64_t ot = uni64(P.offsets[t]), lt = uni64(P.offsets[t + 1]) - ot;
   if (k < 0 || qp < 0 || tp < 0 || qp + (int64_t)k > lq ||
       tp + (int64_t)k > lt) {
     s.status = S_RANGE;
     return s;
   }
-  if (P.seq_bad && (P.seq_bad[q] == 2 || P.seq_bad[t] == 2)) {
+  if (P.seq_bad && (uni(P.seq_bad[q]) == 2 || uni(P.seq_bad[t]) == 2)) {
     s.status = S_SYMBOL;
     return s;
   }
@@ -525,10 +623,11 @@ __device__ __forceinline__ ItemSetup setup_item(const Params& P, int item) {
   e.m = (int)m; e.n = (int)n;
   e.d = 1; e.base = 0;
   e.T = 0; e.bx = 0; e.by = 0;
-  e.L1 = 0; e.U1 = 0; e.alive1 = 1;  // antidiagonal 0: S(0,0) = 0
-  e.L2 = 0; e.U2 = 0; e.alive2 = 0;
+  e.L1 = 0; e.U1 = 0;            // antidiagonal 0: S(0,0) = 0
+  e.L2 = DEAD_L; e.U2 = DEAD_U;  // antidiagonal -1: empty
   e.W = 1;
   e.loaded_a = 0; e.loaded_b = 0;
+  e.q = 0; e.qn = 0; e.qi = 0;
   return s;
 }
 
