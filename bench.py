@@ -35,6 +35,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_digest() -> str:
+    """sha256 of the kernel sources: HBM byte counters stored under profiles/
+    apply only to the kernel build they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_2304_08662_amd/csrc/xdrop_kernels.hip",
+                "paper_2304_08662_amd/csrc/xdrop_internal.h"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the wave kernel from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload, if it was taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel source sha256") != kernel_source_digest():
+        return None
+    try:
+        return int(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def scoring_for(xdrop, scheme):
     if scheme.alphabet == 4 and scheme.matrix is None:
         return xdrop.ScoringSpec(xdrop.DNA2, 4, scheme.match, scheme.mismatch,
@@ -143,6 +176,12 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune variant / tile / chunk on this batch first; "
+                         "the timed steps then use the tuned choice")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB five "
+                         "times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -153,6 +192,16 @@ def main():
     import torch
     from paper_2304_08662_amd import inputs, xdrop
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written":
+                          nbytes, "copies": 5}), flush=True)
+        return
     log(f"generating {args.workload} x{args.scale}")
     batch, scheme = inputs.workload(args.workload, args.scale)
     n = len(batch.seeds)
@@ -165,6 +214,15 @@ def main():
     opts = xdrop.options(args.variant, args.tile, args.chunk)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
+    tuned = None
+    if args.autotune:
+        log("autotune")
+        best = ctx.autotune(d_seqs, d_offs, d_seeds, sc, res, stream=stream)
+        stream.synchronize()
+        tuned = {"variant": best.variant, "tile": best.tile,
+                 "chunk": best.chunk}
+        log(f"tuned {tuned}")
+        opts = None  # automatic: the context now holds the tuned choice
     ctx.set_timing(True)
 
     def step():
@@ -222,11 +280,12 @@ def main():
         "live_gcups": round(live / (ms_step / 1e3) / 1e9, 1),
         "live_cells": live,
         "phase_ms": dict(zip(names, [round(float(x), 4) for x in phase])),
+        "tuned": tuned,
         "roofline": {"bound": "alu", "kernel": names[dom],
                      "achieved": round(achieved, 3),
                      "peak": round(INT32_PEAK_TOPS, 1), "unit": "TOP/s",
                      "frac": round(achieved / INT32_PEAK_TOPS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic(args.workload)},
     }
     ctx.close()
     if args.serve_requests > 0:

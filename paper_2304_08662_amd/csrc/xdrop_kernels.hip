@@ -371,6 +371,39 @@ __device__ __forceinline__ void reload_syms(Ext& e, Syms<ALPHA, C>& sy,
   e.qn = 0;
 }
 
+// ------------------------------------------------------------------ window
+enum { MV_NONE = 0, MV_MOVED = 1, MV_ESC = 2 };
+
+// Keeps the band of antidiagonal e.d inside the window, given the finite
+// ranges [La, Ua] of e.d - 1 and [Lb, Ub] of e.d - 2 (A and B hold those
+// antidiagonals).  If the band can reach past the top, the window slides up
+// by as many whole lanes as the dead cells below the band allow (cells below
+// min(La, Lb) are -infinity on both) and the symbols are reloaded; MV_ESC
+// when not even one lane is free (the caller widens the tile).
+template <int ALPHA, int C>
+__device__ __forceinline__ int window_move(Ext& e, int (&A)[C], int (&B)[C],
+                                           Syms<ALPHA, C>& sy,
+                                           WaveLds<ALPHA>& w, const Src& S,
+                                           int La, int Lb, int Ua, int Ub) {
+  constexpr int LOG2C = C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : 3;
+  const int hi_next = smin(smax(Ua, Ub) + 1, smin(e.m, e.d));
+  if (hi_next <= e.base + 64 * C - 1) return MV_NONE;
+  const int sl = (smin(La, Lb) - e.base) >> LOG2C;
+  if (sl < 1) return MV_ESC;
+  const int src = lane_id() + sl;
+  const bool in = src < 64;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int pa = __builtin_amdgcn_ds_bpermute((src & 63) << 2, A[j]);
+    const int pb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, B[j]);
+    A[j] = in ? pa : NEG;
+    B[j] = in ? pb : NEG;
+  }
+  e.base += sl << LOG2C;
+  reload_syms<ALPHA, C>(e, sy, w, S);
+  return MV_MOVED;
+}
+
 // ------------------------------------------------------------------ step
 // Computes antidiagonal e.d.  On entry A holds d-1 and B holds d-2; on exit
 // A holds d and B holds d-1.  The body is straight-line code with three
@@ -479,27 +512,11 @@ __device__ __forceinline__ int step(Ext& e, int (&A)[C], int (&B)[C],
   if ((!any && L1 > U1) || d >= e.m + e.n) r = R_DONE;
 
   // keep the next antidiagonal's band inside the window
-  const int hi_next = smin(smax(U0, U1) + 1, smin(e.m, d + 1));
-  if (r == R_CONT && hi_next > e.base + 64 * C - 1) {
-    // slide the window up by as many whole lanes as the dead cells below
-    // the band allow (cells below min(L0, L1) are -infinity on d and d-1)
-    const int sl = (smin(L0, L1) - e.base) >> LOG2C;
-    if (sl < 1) {
-      r = R_ESC;
-    } else {
-      const int src = lane + sl;
-      const bool in = src < 64;
-#pragma unroll
-      for (int j = 0; j < C; ++j) {
-        const int pa = __builtin_amdgcn_ds_bpermute((src & 63) << 2, A[j]);
-        const int pb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, B[j]);
-        A[j] = in ? pa : NEG;
-        B[j] = in ? pb : NEG;
-      }
-      e.base += sl << LOG2C;
-      reload_syms<ALPHA, C>(e, sy, w, S);
-    }
-  } else if (r == R_CONT) {
+  int mv = MV_NONE;
+  if (r == R_CONT) mv = window_move<ALPHA, C>(e, A, B, sy, w, S, L0, L1, U0, U1);
+  if (mv == MV_ESC) {
+    r = R_ESC;
+  } else if (r == R_CONT && mv == MV_NONE) {
     // target codes of the next antidiagonal: one code enters at lane 0
     if (e.qn == 0) {
       cover_b<ALPHA>(e, w, S, e.qi + Syms<ALPHA, C>::QCODES - 1);
@@ -514,6 +531,152 @@ __device__ __forceinline__ int step(Ext& e, int (&A)[C], int (&B)[C],
     sy.advance(in);
   }
   if (cap_hit) r = R_CAP;
+  make_uniform(e);
+  return r;
+}
+
+// ------------------------------------------------------------------ interior
+// A value that the compiler keeps in a VGPR (a loop-invariant operand of a
+// per-lane select, which may not read two SGPRs).
+__device__ __forceinline__ int in_vgpr(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0xE4, 0xf, 0xf, false);
+}
+
+// Lean sweep for one cell per lane while every window cell of the
+// antidiagonals it computes lies inside the matrix (d - n <= base and
+// base + 63 <= m) and no band cap is set.  There the band needs no clamps,
+// so its bookkeeping runs on the finite-lane ballots M1, M2 of the last two
+// antidiagonals instead of on scalar ranges:
+//   lo_d - base = lowest set bit of (M1 | M2 << 1),
+//   hi_d - base = highest set bit of (M1 | M2) + 1.
+// The top lane stays -infinity here (the loop hands over as soon as the band
+// reaches it), so the neighbour exchange is a wave rotation that brings that
+// -infinity to lane 0.  Symbols are kept as bare codes (DNA: the 2-bit code;
+// bytes: the target code and 32 x the query code, a table row), and the code
+// entering lane 0 comes from a register queue refilled from the ring.
+// Returns R_CONT, with the state the generic step expects, at the first
+// antidiagonal it does not handle (band reaching the top lane, two
+// antidiagonals without finite cells, the end of the interior), or R_ESC
+// when the band fills the window.
+template <int ALPHA>
+__device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
+                                             Syms<ALPHA, 1>& sy,
+                                             WaveLds<ALPHA>& w,
+                                             const int* tab, const Params& P,
+                                             const Src& S) {
+  const int base = e.base;
+  if (P.band_cap > 0 || e.m - base < 63 || e.d > e.n + base) return R_CONT;
+  uint64_t m1 = e.L1 > e.U1 ? 0
+                : (1ull << (e.L1 - base)) | (1ull << (e.U1 - base));
+  uint64_t m2 = e.L2 > e.U2 ? 0
+                : (1ull << (e.L2 - base)) | (1ull << (e.U2 - base));
+  const uint64_t chi = m1 | m2;
+  if (chi == 0 || (chi >> 63)) return R_CONT;
+  // leading zeros of M1 | M2: 64 when both antidiagonals are dead, 0 when
+  // the top lane holds a finite cell (the two cases the loop hands over on)
+  int cz = (int)__builtin_clzg(chi, 64);
+  const int d0 = e.d;
+  const int d_end = smin(e.n + base, d0 + (1 << 20));  // 32-bit sums exact
+  const int gap = P.gap, X = P.X;
+  const int lane = lane_id();
+  const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
+  int fa, fb;
+  if constexpr (ALPHA == 0) {
+    fa = (int)(Ring<0>::read(w.ra, base + lane - 1) & 3u);
+    fb = (int)(Ring<0>::read(w.rb, d0 - base - lane - 1) & 3u);
+  } else {
+    uint32_t t[1];
+    Ring<1>::read<1>(w.ra, base + lane - 1, t);
+    fa = (int)(t[0] & 31u) << 5;
+    Ring<1>::read<1>(w.rb, d0 - base - lane - 1, t);
+    fb = (int)(t[0] & 31u);
+  }
+  int d = d0;
+  int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
+  uint32_t acc = 0;         // sum over d of (ctz(lo mask) + clz(hi mask))
+
+  // antidiagonal d from prev (d-1) and pp (d-2); pp receives d.  Then the
+  // target codes move one cell up and lane 0 takes `in` (b[d - base]).
+  auto body = [&](int& prev, int& pp, int in) -> bool {
+    acc += (uint32_t)(__builtin_ctzll(m1 | (m2 << 1)) + cz);
+    const int thr = smax(tv - X, THR_FLOOR);
+    const int up = __builtin_amdgcn_mov_dpp(prev, 0x13C, 0xf, 0xf, false);
+    const int dg = __builtin_amdgcn_mov_dpp(pp, 0x13C, 0xf, 0xf, false);
+    int sim;
+    if constexpr (ALPHA == 0) sim = fa == fb ? vmat : vmis;
+    else sim = tab[fa + fb];
+    const int v = max(max(up, prev), dg + sim);
+    const bool f = v >= thr;
+    const int vn = f ? v : NEG;
+    const uint64_t fm = ballot(f);
+    const uint64_t imp = ballot(vn > tv);
+    pp = vn;
+    if (imp) {
+      int wm, l0;
+      if (__builtin_popcountll(imp) == 1) {
+        l0 = __builtin_ctzll(imp);
+        wm = __builtin_amdgcn_readlane(vn, l0);
+      } else {
+        wm = uni(wave_max(vn));
+        l0 = __builtin_ctzll(ballot(vn == wm));
+      }
+      tv = wm;
+      e.T = wm + gap * d;
+      e.bx = base + l0;
+      e.by = d - e.bx;
+    }
+    m2 = m1;
+    m1 = fm;
+    cz = (int)__builtin_clzg(fm | m2, 64);
+    tv -= gap;
+    ++d;
+    // (on a hand-over the symbols are reloaded, so this move is harmless)
+    fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
+    return (uint32_t)(cz - 1) < 63u;
+  };
+  // blocks of 16 antidiagonals; the 16 codes entering lane 0 during a block
+  // are read from the ring at its start
+  int x = A[0], y = B[0];
+  bool newest_in_y = false;
+  while (d + 15 <= d_end) {
+    const int e0 = d - base;
+    cover_b<ALPHA>(e, w, S, e0 + 15);
+    uint32_t qw[ALPHA == 0 ? 1 : 4];
+    if constexpr (ALPHA == 0) {
+      qw[0] = Ring<0>::read(w.rb, e0);
+    } else {
+      Ring<1>::read<4>(w.rb, e0, qw);
+    }
+#pragma unroll
+    for (int i = 0; i < (ALPHA == 0 ? 1 : 4); ++i)
+      qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+#pragma unroll
+    for (int k = 0; k < 16; k += 2) {
+      const int in0 = ALPHA == 0
+          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
+          : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
+      const int in1 = ALPHA == 0
+          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
+          : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
+      if (!body(x, y, in0)) { newest_in_y = true; goto done; }
+      if (!body(y, x, in1)) { newest_in_y = false; goto done; }
+    }
+  }
+done:
+  A[0] = newest_in_y ? y : x;
+  B[0] = newest_in_y ? x : y;
+
+  e.d = d;
+  e.W += (int64_t)65 * (d - d0) - (int64_t)acc;
+  e.L1 = m1 ? base + __builtin_ctzll(m1) : DEAD_L;
+  e.U1 = m1 ? base + 63 - __builtin_clzll(m1) : DEAD_U;
+  e.L2 = m2 ? base + __builtin_ctzll(m2) : DEAD_L;
+  e.U2 = m2 ? base + 63 - __builtin_clzll(m2) : DEAD_U;
+  int r = R_CONT;
+  const int mv = window_move<ALPHA, 1>(e, A, B, sy, w, S, e.L1, e.L2, e.U1,
+                                       e.U2);
+  if (mv == MV_ESC) r = R_ESC;
+  else if (mv == MV_NONE) reload_syms<ALPHA, 1>(e, sy, w, S);
   make_uniform(e);
   return r;
 }
@@ -545,6 +708,10 @@ __device__ int run_tier(Ext& e, int (&A)[C], int (&B)[C], WaveLds<ALPHA>& w,
     reload_syms<ALPHA, C>(e, sy, w, S);
     make_uniform(e);
     do {
+      if constexpr (C == 1) {
+        r = fast_interior<ALPHA>(e, A, B, sy, w, tab, P, S);
+        if (r != R_CONT) break;
+      }
       r = step<ALPHA, C>(e, A, B, sy, w, tab, P, S);
     } while (r == R_CONT);
   }
@@ -927,13 +1094,26 @@ __global__ void xd_scan_kernel(int32_t* counters) {
   counters[C_CURSOR + b] = v[b] - counters[C_HIST + b];
 }
 
+// Items of one block claim their slots bucket by bucket: one device atomic
+// per (block, bucket) instead of one per item.
 __global__ void xd_scatter_kernel(const int32_t* seeds, const int64_t* offsets,
                                   int32_t n_seqs, int32_t n_items,
                                   int32_t* counters, int32_t* order) {
+  __shared__ int h[NBUCKET];
+  __shared__ int first[NBUCKET];
+  for (int b = threadIdx.x; b < NBUCKET; b += blockDim.x) h[b] = 0;
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_items) return;
-  const int b = cost_bucket(seeds, offsets, n_seqs, i);
-  order[atomicAdd(counters + C_CURSOR + b, 1)] = i;
+  int b = 0, rank = 0;
+  if (i < n_items) {
+    b = cost_bucket(seeds, offsets, n_seqs, i);
+    rank = atomicAdd(&h[b], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < NBUCKET; c += blockDim.x)
+    first[c] = h[c] ? atomicAdd(counters + C_CURSOR + c, h[c]) : 0;
+  __syncthreads();
+  if (i < n_items) order[first[b] + rank] = i;
 }
 
 // Seed level: score = left + seed score + right and positions (Sec. 4.1.1).

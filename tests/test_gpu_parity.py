@@ -135,6 +135,30 @@ def test_workloads_small(runner, name, scale):
     assert not bad, bad[:10]
 
 
+@pytest.mark.parametrize("name,n_sample,tail", [
+    ("dna-1k", 200, 0),
+    ("dna-tail", 40, 20),
+    ("protein-500k", 300, 0)])
+def test_full_size_sampled(runner, name, n_sample, tail):
+    """The whole workload in one launch, as bench.py times it (automatic
+    options: persistent queue, longest first); a seeded random sample of
+    seeds, plus the first `tail` long-tail seeds, checked against the oracle
+    one by one."""
+    batch, scheme = inputs.workload(name, 1.0)
+    g = runner.run(batch, scheme)
+    assert (g["status"] == 0).all()
+    n = len(batch.seeds)
+    rng = np.random.default_rng(99)
+    idx = set(rng.choice(n, size=min(n_sample, n), replace=False).tolist())
+    if tail:  # the long pairs are the last ones of the batch
+        n_tail = int(np.sum(np.diff(batch.offsets)[1::2] > 40000))
+        idx |= set(range(n - n_tail, n - n_tail + tail))
+    idx = sorted(idx)
+    ref = oracle_run(batch.subset(idx), scheme)
+    bad = compare(g[idx], ref)
+    assert not bad, bad[:10]
+
+
 def test_variants_identical(runner):
     from paper_2304_08662_amd import xdrop
     rng = np.random.default_rng(23)
