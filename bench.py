@@ -92,25 +92,30 @@ def cpu_baseline(batch, scheme, target_s: float, gpu_cells_per_seed):
     per_seed = dt / max(len(probe.seeds), 1)
     k = int(min(n, max(50, target_s / max(per_seed, 1e-6))))
     sample = batch.subset(order[:k])
-    t0 = time.perf_counter()
-    out, th = oracle.batch(sample.codes, sample.offsets, sample.seeds, sc)
-    dt = time.perf_counter() - t0
-    cells = sample.gcups_cells()
+    # a workload smaller than the target runs whole, repeated
+    reps, dt = 0, 0.0
+    while reps == 0 or (dt < target_s / 2 and reps < 40):
+        t0 = time.perf_counter()
+        out, th = oracle.batch(sample.codes, sample.offsets, sample.seeds, sc)
+        dt += time.perf_counter() - t0
+        reps += 1
+    cells = sample.gcups_cells() * reps
     return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS",
             "cores": int(th), "kind": "oracle",
-            "sample": f"{k} of {n} seeds (random, seed 7), {dt:.1f} s, "
-                      f"{int(out['cells'].sum())} live cells, "
-                      f"aln/s {k / dt:.1f}"}
+            "sample": f"{k} of {n} seeds (random, seed 7) x {reps}, "
+                      f"{dt:.1f} s, {int(out['cells'].sum())} live cells per "
+                      f"pass, aln/s {k * reps / dt:.1f}"}
 
 
 def serving_run(xdrop, n_requests: int, rates=(0.8,), budget=64 << 30):
-    """Poisson request stream (1-4096 pairs, DNA 1k-generator or protein
-    generator): saturation throughput from a closed burst, then p50/p99
-    latency at the given fractions of it."""
+    """Poisson request stream (1-4096 pairs, log-uniform; DNA 1k-generator or
+    protein-generator pairs drawn from pools): saturation throughput from a
+    closed burst, then p50/p99 latency at the given fractions of it."""
     from paper_2304_08662_amd import inputs
     srv = xdrop.Server(0, budget_bytes=budget)
     rng = inputs.rng_for(5)
-    reqs = [(b, s) for _, b, s in inputs.request_stream(rng, n_requests, 0.0)]
+    reqs = [(b, s) for _, b, s in
+            inputs.request_stream_pooled(rng, n_requests, 0.0)]
     packed = [(b.packed() if b.alphabet == 4 else b.codes) for b, _ in reqs]
     scs = [scoring_for(xdrop, s) for _, s in reqs]
     # saturation: everything at once
@@ -171,8 +176,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--serve-rates", default="0.8")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="0.5,0.8,0.95")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)

@@ -577,7 +577,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int cz = (int)__builtin_clzg(chi, 64);
   const int d0 = e.d;
   const int d_end = smin(e.n + base, d0 + (1 << 20));  // 32-bit sums exact
-  const int gap = P.gap, X = P.X;
+  // every finite V lies in [-2^28, 2^28] and T's frame value tv in
+  // [0, 2^28] (value bound checked per extension), so capping X at 2^29
+  // prunes exactly the same cells and keeps tv - X above the floor
+  const int gap = P.gap, X = smin(P.X, 1 << 29);
   const int lane = lane_id();
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
   int fa, fb;
@@ -594,12 +597,13 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
   uint32_t acc = 0;         // sum over d of (ctz(lo mask) + clz(hi mask))
+  int tbest = 0, bd = -1, bl = 0;  // last new best: V value, antidiagonal, lane
 
   // antidiagonal d from prev (d-1) and pp (d-2); pp receives d.  Then the
   // target codes move one cell up and lane 0 takes `in` (b[d - base]).
   auto body = [&](int& prev, int& pp, int in) -> bool {
     acc += (uint32_t)(__builtin_ctzll(m1 | (m2 << 1)) + cz);
-    const int thr = smax(tv - X, THR_FLOOR);
+    const int thr = tv - X;
     const int up = __builtin_amdgcn_mov_dpp(prev, 0x13C, 0xf, 0xf, false);
     const int dg = __builtin_amdgcn_mov_dpp(pp, 0x13C, 0xf, 0xf, false);
     int sim;
@@ -612,18 +616,17 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     const uint64_t imp = ballot(vn > tv);
     pp = vn;
     if (imp) {
-      int wm, l0;
-      if (__builtin_popcountll(imp) == 1) {
-        l0 = __builtin_ctzll(imp);
-        wm = __builtin_amdgcn_readlane(vn, l0);
-      } else {
+      // usually a single lane beats T: its value is the new best
+      int l0 = __builtin_ctzll(imp);
+      int wm = __builtin_amdgcn_readlane(vn, l0);
+      if (imp & (imp - 1)) {
         wm = uni(wave_max(vn));
         l0 = __builtin_ctzll(ballot(vn == wm));
       }
       tv = wm;
-      e.T = wm + gap * d;
-      e.bx = base + l0;
-      e.by = d - e.bx;
+      tbest = wm;  // T, bx, by are formed on hand-over
+      bd = d;
+      bl = l0;
     }
     m2 = m1;
     m1 = fm;
@@ -668,6 +671,11 @@ done:
 
   e.d = d;
   e.W += (int64_t)65 * (d - d0) - (int64_t)acc;
+  if (bd >= 0) {
+    e.T = tbest + gap * bd;
+    e.bx = base + bl;
+    e.by = bd - e.bx;
+  }
   e.L1 = m1 ? base + __builtin_ctzll(m1) : DEAD_L;
   e.U1 = m1 ? base + 63 - __builtin_clzll(m1) : DEAD_U;
   e.L2 = m2 ? base + __builtin_ctzll(m2) : DEAD_L;
@@ -677,6 +685,182 @@ done:
                                        e.U2);
   if (mv == MV_ESC) r = R_ESC;
   else if (mv == MV_NONE) reload_syms<ALPHA, 1>(e, sy, w, S);
+  make_uniform(e);
+  return r;
+}
+
+// The interior loop for C = 2 or 4 cells per lane.  Same hand-over rules as
+// for one cell per lane; the finite range of an antidiagonal, relative to
+// base, comes from its per-register ballots (cell j of lane l is window
+// position C*l + j): L = min_j C*ctz(M_j) + j, U = max_j C*(63 - clz(M_j)) + j
+// (an empty antidiagonal gives L = 64*C, U = -1).  The top cell of the
+// window (position 64*C - 1) stays -infinity, so the rotation brings
+// -infinity to lane 0.
+template <int ALPHA, int C>
+__device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
+                                                   int (&B)[C],
+                                                   Syms<ALPHA, C>& sy,
+                                                   WaveLds<ALPHA>& w,
+                                                   const int* tab,
+                                                   const Params& P,
+                                                   const Src& S) {
+  constexpr int TOP = 64 * C - 1;
+  constexpr int LOG2C = C == 2 ? 1 : 2;
+  const int base = e.base;
+  if (P.band_cap > 0 || e.m - base < TOP || e.d > e.n + base) return R_CONT;
+  int L1 = e.L1 > e.U1 ? 64 * C : e.L1 - base;
+  int U1 = e.L1 > e.U1 ? -1 : e.U1 - base;
+  int L2 = e.L2 > e.U2 ? 64 * C : e.L2 - base;
+  int U2 = e.L2 > e.U2 ? -1 : e.U2 - base;
+  if ((uint32_t)smax(U1, U2) >= (uint32_t)TOP) return R_CONT;
+  const int d0 = e.d;
+  const int d_end = smin(e.n + base, d0 + (1 << 20));  // 32-bit sums exact
+  // every finite V lies in [-2^28, 2^28] and T's frame value tv in
+  // [0, 2^28] (value bound checked per extension), so capping X at 2^29
+  // prunes exactly the same cells and keeps tv - X above the floor
+  const int gap = P.gap, X = smin(P.X, 1 << 29);
+  const int lane = lane_id();
+  const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
+  // bare codes: cell j of lane l is x = base + C*l + j and takes
+  // a[x - 1] and b[d - x - 1]
+  int fa[C], fb[C];
+  {
+    const int sa = base + lane * C - 1;
+    const int sb = d0 - base - lane * C - C;  // b index of cell C-1
+    if constexpr (ALPHA == 0) {
+      const uint32_t wa = Ring<0>::read(w.ra, sa);
+      const uint32_t wb = Ring<0>::read(w.rb, sb);
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        fa[j] = (int)((wa >> (2 * j)) & 3u);
+        fb[j] = (int)((wb >> (2 * (C - 1 - j))) & 3u);
+      }
+    } else {
+      uint32_t ta[1], tb[1];
+      Ring<1>::read<1>(w.ra, sa, ta);
+      Ring<1>::read<1>(w.rb, sb, tb);
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        fa[j] = (int)((ta[0] >> (8 * j)) & 31u) << 5;
+        fb[j] = (int)((tb[0] >> (8 * (C - 1 - j))) & 31u);
+      }
+    }
+  }
+  int d = d0;
+  int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
+  uint32_t acc = 0;         // live-span cells of the antidiagonals done
+  int tbest = 0, bd = -1, bx_rel = 0;
+
+  // antidiagonal d from prev (d-1) and pp (d-2); pp receives d
+  auto body = [&](int (&prev)[C], int (&pp)[C], int in) -> bool {
+    acc += (uint32_t)(smax(U1, U2) - smin(L1, L2 + 1) + 2);
+    const int thr = tv - X;
+    int v[C];
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j) {
+      const int up = j ? prev[j - 1]
+                       : __builtin_amdgcn_mov_dpp(prev[C - 1], 0x13C, 0xf,
+                                                  0xf, false);
+      const int dg = j ? pp[j - 1]
+                       : __builtin_amdgcn_mov_dpp(pp[C - 1], 0x13C, 0xf, 0xf,
+                                                  false);
+      int sim;
+      if constexpr (ALPHA == 0) sim = fa[j] == fb[j] ? vmat : vmis;
+      else sim = tab[fa[j] + fb[j]];
+      v[j] = max(max(up, prev[j]), dg + sim);
+    }
+    int L0 = 64 * C, U0 = -1, lm = NEG;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const bool f = v[j] >= thr;
+      pp[j] = f ? v[j] : NEG;
+      lm = max(lm, pp[j]);
+      const uint64_t fm = ballot(f);
+      L0 = smin(L0, ((int)__builtin_ctzg(fm, 64) << LOG2C) + j);
+      U0 = smax(U0, ((63 - (int)__builtin_clzg(fm, 64)) << LOG2C) + j);
+    }
+    const uint64_t imp = ballot(lm > tv);
+    if (imp) {
+      int l0 = __builtin_ctzll(imp);
+      int wm = __builtin_amdgcn_readlane(lm, l0);
+      if (imp & (imp - 1)) {
+        wm = uni(wave_max(lm));
+        l0 = __builtin_ctzll(ballot(lm == wm));
+      }
+      int jf = C - 1;
+#pragma unroll
+      for (int j = C - 1; j >= 0; --j)
+        if (pp[j] == wm) jf = j;
+      tv = wm;
+      tbest = wm;  // T, bx, by are formed on hand-over
+      bd = d;
+      bx_rel = (l0 << LOG2C) + __builtin_amdgcn_readlane(jf, l0);
+    }
+    L2 = L1; U2 = U1;
+    L1 = L0; U1 = U0;
+    tv -= gap;
+    ++d;
+    // the target codes move one cell up; lane 0 takes `in`
+    const int top = fb[C - 1];
+#pragma unroll
+    for (int j = C - 1; j > 0; --j) fb[j] = fb[j - 1];
+    fb[0] = __builtin_amdgcn_update_dpp(in, top, 0x138, 0xf, 0xf, false);
+    return (uint32_t)smax(U0, U2) < (uint32_t)TOP;
+  };
+  // blocks of QB antidiagonals; the codes entering lane 0 during a block
+  // are read from the ring at its start
+  int x[C], y[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) { x[j] = A[j]; y[j] = B[j]; }
+  bool newest_in_y = false;
+  // (blocks of 8 for byte codes keep the register footprint small)
+  constexpr int QB = ALPHA == 0 ? 16 : 8;
+  while (d + QB - 1 <= d_end) {
+    const int e0 = d - base;
+    cover_b<ALPHA>(e, w, S, e0 + QB - 1);
+    uint32_t qw[ALPHA == 0 ? 1 : 2];
+    if constexpr (ALPHA == 0) {
+      qw[0] = Ring<0>::read(w.rb, e0);
+    } else {
+      Ring<1>::read<2>(w.rb, e0, qw);
+    }
+#pragma unroll
+    for (int i = 0; i < (ALPHA == 0 ? 1 : 2); ++i)
+      qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+#pragma unroll
+    for (int k = 0; k < QB; k += 2) {
+      const int in0 = ALPHA == 0
+          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
+          : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
+      const int in1 = ALPHA == 0
+          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
+          : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
+      if (!body(x, y, in0)) { newest_in_y = true; goto done; }
+      if (!body(y, x, in1)) { newest_in_y = false; goto done; }
+    }
+  }
+done:
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    A[j] = newest_in_y ? y[j] : x[j];
+    B[j] = newest_in_y ? x[j] : y[j];
+  }
+  e.d = d;
+  e.W += (int64_t)acc;
+  if (bd >= 0) {
+    e.T = tbest + gap * bd;
+    e.bx = base + bx_rel;
+    e.by = bd - e.bx;
+  }
+  e.L1 = U1 < 0 ? DEAD_L : base + L1;
+  e.U1 = U1 < 0 ? DEAD_U : base + U1;
+  e.L2 = U2 < 0 ? DEAD_L : base + L2;
+  e.U2 = U2 < 0 ? DEAD_U : base + U2;
+  int r = R_CONT;
+  const int mv = window_move<ALPHA, C>(e, A, B, sy, w, S, e.L1, e.L2, e.U1,
+                                       e.U2);
+  if (mv == MV_ESC) r = R_ESC;
+  else if (mv == MV_NONE) reload_syms<ALPHA, C>(e, sy, w, S);
   make_uniform(e);
   return r;
 }
@@ -710,6 +894,9 @@ __device__ int run_tier(Ext& e, int (&A)[C], int (&B)[C], WaveLds<ALPHA>& w,
     do {
       if constexpr (C == 1) {
         r = fast_interior<ALPHA>(e, A, B, sy, w, tab, P, S);
+        if (r != R_CONT) break;
+      } else if constexpr (C == 2) {
+        r = fast_interior_multi<ALPHA, C>(e, A, B, sy, w, tab, P, S);
         if (r != R_CONT) break;
       }
       r = step<ALPHA, C>(e, A, B, sy, w, tab, P, S);

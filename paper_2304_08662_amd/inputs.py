@@ -298,6 +298,37 @@ def concat(a: Batch, b: Batch, meta=None) -> Batch:
                  meta if meta is not None else dict(a.meta))
 
 
+def request_stream_pooled(rng, n_requests: int, mean_gap_s: float,
+                          max_pairs=4096, pool_pairs=8192):
+    """As request_stream, but each request takes a contiguous run of pairs
+    (cyclic) at a random start from one of two pools generated once: DNA
+    pairs of the 1k generator and protein pairs of the protein generator.
+    Request sizes, arrivals and the DNA/protein mix follow the same laws; the
+    pools make long streams cheap to generate (pairs repeat across
+    requests).  Yields (arrival_time_s, Batch, Scheme)."""
+    dna_scheme = Scheme(4, 1, -1, -1, 15)
+    prot_scheme = Scheme(20, gap=-2, X=49,
+                         matrix=stand_in_substitution_matrix())
+    L = rng.integers(1000, 2001, pool_pairs)
+    dna_pool = _assemble(dna_pairs(rng, pool_pairs, L, 0.15, 17, 1.0, True),
+                         4, {"pool": "dna"})
+    L = rng.integers(50, 1001, pool_pairs)
+    prot_pool = _assemble(protein_pairs(rng, pool_pairs, L, 6, 0.5), 20,
+                          {"pool": "protein"})
+    t = 0.0
+    for r in range(n_requests):
+        t += float(rng.exponential(mean_gap_s))
+        size = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(max_pairs + 1)))),
+                           1, max_pairs))
+        pool, scheme = ((dna_pool, dna_scheme) if rng.random() < 0.5
+                        else (prot_pool, prot_scheme))
+        start = int(rng.integers(0, pool_pairs))
+        idx = (start + np.arange(size)) % pool_pairs
+        b = pool.subset(idx)
+        b.meta = {"request": r}
+        yield t, b, scheme
+
+
 def request_stream(rng, n_requests: int, mean_gap_s: float, max_pairs=4096):
     """Serving workload: Poisson arrivals; each request holds
     floor(exp(U(ln 1, ln 4097))) pairs (clipped to [1, 4096]), DNA (1k
