@@ -31,6 +31,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "xdrop_internal.h"
 
@@ -542,67 +543,91 @@ __device__ __forceinline__ int in_vgpr(int v) {
   return __builtin_amdgcn_update_dpp(0, v, 0xE4, 0xf, 0xf, false);
 }
 
-// Lean sweep for one cell per lane while every window cell of the
-// antidiagonals it computes lies inside the matrix (d - n <= base and
-// base + 63 <= m) and no band cap is set.  There the band needs no clamps,
-// so its bookkeeping runs on the finite-lane ballots M1, M2 of the last two
-// antidiagonals instead of on scalar ranges:
-//   lo_d - base = lowest set bit of (M1 | M2 << 1),
-//   hi_d - base = highest set bit of (M1 | M2) + 1.
-// The top lane stays -infinity here (the loop hands over as soon as the band
-// reaches it), so the neighbour exchange is a wave rotation that brings that
-// -infinity to lane 0.  Symbols are kept as bare codes (DNA: the 2-bit code;
-// bytes: the target code and 32 x the query code, a table row), and the code
-// entering lane 0 comes from a register queue refilled from the ring.
-// Returns R_CONT, with the state the generic step expects, at the first
-// antidiagonal it does not handle (band reaching the top lane, two
-// antidiagonals without finite cells, the end of the interior), or R_ESC
-// when the band fills the window.
+// Lean sweep for one cell per lane.  The band bookkeeping runs on the
+// finite-lane ballots M1, M2 of the last two antidiagonals instead of on
+// scalar ranges (positions relative to the window base):
+//   lo_d = max(ctz(M1 | M2 << 1), d - n - base),
+//   hi_d = min(64 - clz(M1 | M2), m - base),
+// where the clamps matter only near the matrix edges; blocks of 16
+// antidiagonals that stay clear of both edges skip them and the per-lane
+// edge masks.  The top lane stays -infinity in this loop, so the neighbour
+// exchange is a wave rotation that brings -infinity to lane 0; when the band
+// reaches the top lane the window slides up in place by the dead lanes below
+// the band.  Symbols are bare codes (DNA: the 2-bit code; bytes: the target
+// code and 32 x the query code, a table row); the 16 codes that enter lane 0
+// during a block are read from the ring at its start.  The loop computes
+// antidiagonals up to m + n - 1 and hands over to the generic step (state as
+// that step expects) at the last one, after two dead antidiagonals, or when
+// the band fills the window; R_ESC when the window can neither slide nor
+// stay.
 template <int ALPHA>
 __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
                                              Syms<ALPHA, 1>& sy,
                                              WaveLds<ALPHA>& w,
                                              const int* tab, const Params& P,
                                              const Src& S) {
-  const int base = e.base;
-  if (P.band_cap > 0 || e.m - base < 63 || e.d > e.n + base) return R_CONT;
+  int base = e.base;
+  if (P.band_cap > 0) return R_CONT;
+  const int d_last = e.m + e.n - 1;  // antidiagonals this loop may compute
+  if (e.d > d_last) return R_CONT;
   uint64_t m1 = e.L1 > e.U1 ? 0
                 : (1ull << (e.L1 - base)) | (1ull << (e.U1 - base));
   uint64_t m2 = e.L2 > e.U2 ? 0
                 : (1ull << (e.L2 - base)) | (1ull << (e.U2 - base));
-  const uint64_t chi = m1 | m2;
-  if (chi == 0 || (chi >> 63)) return R_CONT;
+  {
+    const uint64_t chi = m1 | m2;
+    if (chi == 0 || (chi >> 63)) return R_CONT;
+  }
   // leading zeros of M1 | M2: 64 when both antidiagonals are dead, 0 when
-  // the top lane holds a finite cell (the two cases the loop hands over on)
-  int cz = (int)__builtin_clzg(chi, 64);
+  // the top lane holds a finite cell (the two cases the loop acts on)
+  int cz = (int)__builtin_clzg(m1 | m2, 64);
   const int d0 = e.d;
-  const int d_end = smin(e.n + base, d0 + (1 << 20));  // 32-bit sums exact
+  const int d_end = smin(d_last, d0 + (1 << 20));  // 32-bit sums exact
   // every finite V lies in [-2^28, 2^28] and T's frame value tv in
   // [0, 2^28] (value bound checked per extension), so capping X at 2^29
   // prunes exactly the same cells and keeps tv - X above the floor
   const int gap = P.gap, X = smin(P.X, 1 << 29);
+  const int m = e.m, n = e.n;
   const int lane = lane_id();
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
   int fa, fb;
+  auto load_fa = [&]() {
+    if constexpr (ALPHA == 0) {
+      fa = (int)(Ring<0>::read(w.ra, base + lane - 1) & 3u);
+    } else {
+      uint32_t t[1];
+      Ring<1>::read<1>(w.ra, base + lane - 1, t);
+      fa = (int)(t[0] & 31u) << 5;
+    }
+  };
+  load_fa();
   if constexpr (ALPHA == 0) {
-    fa = (int)(Ring<0>::read(w.ra, base + lane - 1) & 3u);
     fb = (int)(Ring<0>::read(w.rb, d0 - base - lane - 1) & 3u);
   } else {
     uint32_t t[1];
-    Ring<1>::read<1>(w.ra, base + lane - 1, t);
-    fa = (int)(t[0] & 31u) << 5;
     Ring<1>::read<1>(w.rb, d0 - base - lane - 1, t);
     fb = (int)(t[0] & 31u);
   }
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
-  uint32_t acc = 0;         // sum over d of (ctz(lo mask) + clz(hi mask))
-  int tbest = 0, bd = -1, bl = 0;  // last new best: V value, antidiagonal, lane
+  uint32_t acc = 0;         // sum over d of (65 - live-span cells)
+  int tbest = 0, bd = -1, bxa = 0;  // last new best: V value, d, x
+  int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
 
-  // antidiagonal d from prev (d-1) and pp (d-2); pp receives d.  Then the
-  // target codes move one cell up and lane 0 takes `in` (b[d - base]).
-  auto body = [&](int& prev, int& pp, int in) -> bool {
-    acc += (uint32_t)(__builtin_ctzll(m1 | (m2 << 1)) + cz);
+  // Antidiagonal d from prev (d-1) and pp (d-2); pp receives d, then the
+  // target codes move one cell up and lane 0 takes `in`.  Returns 0 to go
+  // on, 1 when the top lane turned finite, 2 after two dead antidiagonals,
+  // 3 (edge blocks) past the last antidiagonal of the range.
+  auto body = [&](auto edge_tag, int& prev, int& pp, int in) -> int {
+    constexpr bool EDGE = decltype(edge_tag)::value;
+    const uint64_t clo = m1 | (m2 << 1);
+    if constexpr (EDGE) {
+      const int lo = smax(__builtin_ctzll(clo), pm);
+      const int hi = smin(64 - cz, mrel);
+      acc += (uint32_t)(65 - smax(hi - lo + 1, 0));
+    } else {
+      acc += (uint32_t)(__builtin_ctzll(clo) + cz);
+    }
     const int thr = tv - X;
     const int up = __builtin_amdgcn_mov_dpp(prev, 0x13C, 0xf, 0xf, false);
     const int dg = __builtin_amdgcn_mov_dpp(pp, 0x13C, 0xf, 0xf, false);
@@ -610,7 +635,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     if constexpr (ALPHA == 0) sim = fa == fb ? vmat : vmis;
     else sim = tab[fa + fb];
     const int v = max(max(up, prev), dg + sim);
-    const bool f = v >= thr;
+    bool f = v >= thr;
+    if constexpr (EDGE)  // y > n below pm, x > m above mrel
+      f = f && (uint32_t)(lane - pm) <= (uint32_t)(mrel - pm);
     const int vn = f ? v : NEG;
     const uint64_t fm = ballot(f);
     const uint64_t imp = ballot(vn > tv);
@@ -626,22 +653,31 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       tv = wm;
       tbest = wm;  // T, bx, by are formed on hand-over
       bd = d;
-      bl = l0;
+      bxa = base + l0;
     }
     m2 = m1;
     m1 = fm;
     cz = (int)__builtin_clzg(fm | m2, 64);
     tv -= gap;
     ++d;
-    // (on a hand-over the symbols are reloaded, so this move is harmless)
+    if constexpr (EDGE) ++pm;
+    // (before a hand-over or a slide the symbols are rebuilt, so this move
+    // is harmless)
     fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
-    return (uint32_t)(cz - 1) < 63u;
+    if ((uint32_t)(cz - 1) >= 63u) return cz == 0 ? 1 : 2;
+    if constexpr (EDGE) {
+      if (d > d_end) return 3;
+    }
+    return 0;
   };
-  // blocks of 16 antidiagonals; the 16 codes entering lane 0 during a block
-  // are read from the ring at its start
+
+  // x holds d-1 and y holds d-2 at the start of a block
   int x = A[0], y = B[0];
   bool newest_in_y = false;
-  while (d + 15 <= d_end) {
+  int st = 0;
+  while (d <= d_end) {
+    pm = d - n - base;
+    mrel = m - base;
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + 15);
     uint32_t qw[ALPHA == 0 ? 1 : 4];
@@ -653,28 +689,62 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
 #pragma unroll
     for (int i = 0; i < (ALPHA == 0 ? 1 : 4); ++i)
       qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+    auto run_block = [&](auto edge_tag) {
 #pragma unroll
-    for (int k = 0; k < 16; k += 2) {
-      const int in0 = ALPHA == 0
-          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
-          : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
-      const int in1 = ALPHA == 0
-          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
-          : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
-      if (!body(x, y, in0)) { newest_in_y = true; goto done; }
-      if (!body(y, x, in1)) { newest_in_y = false; goto done; }
-    }
+      for (int k = 0; k < 16; k += 2) {
+        const int in0 = ALPHA == 0
+            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
+            : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
+        const int in1 = ALPHA == 0
+            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
+            : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
+        st = body(edge_tag, x, y, in0);
+        if (st) { newest_in_y = true; return; }
+        st = body(edge_tag, y, x, in1);
+        if (st) { newest_in_y = false; return; }
+      }
+    };
+    if (pm + 15 <= 0 && mrel >= 63 && d + 15 <= d_end)
+      run_block(std::false_type{});
+    else
+      run_block(std::true_type{});
+    if (st == 0) continue;  // 16 antidiagonals done; x holds the newest
+    if (st != 1) break;
+    // the top lane turned finite: slide the window up by the lanes below
+    // the lowest finite cell of d and d-1 (they are -infinity on both)
+    const int sl = __builtin_ctzll(m1 | m2);
+    if (sl < 1) break;
+    const int src = lane + sl;
+    const bool in = src < 64;
+    const int nw = newest_in_y ? y : x;
+    const int od = newest_in_y ? x : y;
+    const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, nw);
+    const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, od);
+    // target codes move with their cells; the top lanes receive stray codes,
+    // which no finite cell uses before they have moved out (a cell there has
+    // a -infinity diagonal predecessor until the band reaches it)
+    fb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb);
+    x = in ? pn : NEG;
+    y = in ? po : NEG;
+    newest_in_y = false;
+    st = 0;
+    m1 >>= sl;
+    m2 >>= sl;
+    cz = (int)__builtin_clzg(m1 | m2, 64);
+    base += sl;
+    cover_a<ALPHA>(e, w, S, base + 62);
+    load_fa();
   }
-done:
   A[0] = newest_in_y ? y : x;
   B[0] = newest_in_y ? x : y;
 
+  e.base = base;
   e.d = d;
   e.W += (int64_t)65 * (d - d0) - (int64_t)acc;
   if (bd >= 0) {
     e.T = tbest + gap * bd;
-    e.bx = base + bl;
-    e.by = bd - e.bx;
+    e.bx = bxa;
+    e.by = bd - bxa;
   }
   e.L1 = m1 ? base + __builtin_ctzll(m1) : DEAD_L;
   e.U1 = m1 ? base + 63 - __builtin_clzll(m1) : DEAD_U;
@@ -883,7 +953,7 @@ __device__ __forceinline__ void widen(const int (&src)[C], int (&dst)[2 * C]) {
 // entry.  The first call may ask for a wider starting tile (start > C); the
 // state is then still the initial one and is widened before any step.
 template <int ALPHA, int C, int CMAX>
-__device__ int run_tier(Ext& e, int (&A)[C], int (&B)[C], WaveLds<ALPHA>& w,
+__device__ __forceinline__ int run_tier(Ext& e, int (&A)[C], int (&B)[C], WaveLds<ALPHA>& w,
                         const int* tab, const Params& P, const Src& S,
                         int start, int& tier_out) {
   int r = R_ESC;
@@ -916,7 +986,7 @@ __device__ int run_tier(Ext& e, int (&A)[C], int (&B)[C], WaveLds<ALPHA>& w,
 }
 
 template <int ALPHA, int CMIN, int CMAX>
-__device__ int start_tier(Ext& e, WaveLds<ALPHA>& w, const int* tab,
+__device__ __forceinline__ int start_tier(Ext& e, WaveLds<ALPHA>& w, const int* tab,
                           const Params& P, const Src& S, int start,
                           int& tier_out) {
   int A[CMIN], B[CMIN];
@@ -990,7 +1060,7 @@ __device__ __forceinline__ int tier_index(int C) {
 }  // the general tier counts at index 5
 
 template <int ALPHA, int CMIN, int CMAX>
-__device__ void run_item(const Params& P, const Src& S, int item,
+__device__ __forceinline__ void run_item(const Params& P, const Src& S, int item,
                          WaveLds<ALPHA>& w, const int* tab) {
   ItemSetup s = setup_item(P, item);
   ItemResult res;
