@@ -259,7 +259,10 @@ def main():
     phase_sum, nb = ctx.last_timing()
     assert nb == args.steps
     phase = np.array(phase_sum) / nb
-    names = ["prep", "wave", "unused", "workgroup", "combine"]
+    # (1) the first extension kernel: the pair kernel in the default form,
+    # else the wave kernel; (2) the wave kernel on the extensions the pair
+    # kernel handed on
+    names = ["prep", "extend", "extend_handed_on", "workgroup", "combine"]
     dom = int(np.argmax(phase))
     achieved = OPS_PER_CELL * live / (phase[dom] / 1e3) / 1e12
     stats = ctx.last_stats()

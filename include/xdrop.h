@@ -96,11 +96,17 @@ typedef struct {
 
 /* Launch options (host struct; NULL = defaults). */
 enum {
-    XDROP_VARIANT_AUTO = 0,      /* choose per batch (tuned table or default) */
+    XDROP_VARIANT_AUTO = 0,      /* choose per batch (tuned table, else WAVE;
+                                    PAIR runs as WAVE when a band cap is set) */
     XDROP_VARIANT_WAVE = 1,      /* one wavefront per extension */
     XDROP_VARIANT_WORKGROUP = 2, /* one 4-wave workgroup per extension */
-    XDROP_VARIANT_PLAIN = 3      /* one wave per extension, one launch wave per
+    XDROP_VARIANT_PLAIN = 3,     /* one wave per extension, one launch wave per
                                     extension, no queue: the baseline form */
+    XDROP_VARIANT_PAIR = 4       /* two extensions per wavefront (32-cell
+                                    windows, one cell per lane); extensions
+                                    whose band outgrows 32 cells restart on
+                                    the wave kernel.  Ignores band_cap (runs
+                                    as WAVE when a cap is set) */
 };
 typedef struct {
     int32_t variant;      /* XDROP_VARIANT_* */
@@ -174,18 +180,20 @@ int xdrop_extend_batch_graph(xdrop_ctx *ctx, const uint8_t *d_seqs,
  * around its launch phases (no host synchronisation).  xdrop_last_timing
  * waits for the last recorded batch, writes to ms[0..n) the durations summed
  * over all batches recorded since timing was switched on or last read --
- * (0) counters, symbol check and longest-first ordering, (1) the wave kernel
- * of 1..8 cells per lane, (2) always 0 in this build, (3) the workgroup
- * tier, (4) the seed-level combine -- sets *batches (optional) to their
- * number, and starts a new record.  Returns XDROP_E_INVALID if none was
- * recorded. */
+ * (0) counters, symbol check and longest-first ordering, (1) the first
+ * extension kernel (the pair kernel for XDROP_VARIANT_PAIR, else the wave
+ * kernel of 1..8 cells per lane), (2) the wave kernel on the extensions the
+ * pair kernel handed on (0 for the other variants), (3) the workgroup tier,
+ * (4) the seed-level combine -- sets *batches (optional) to their number,
+ * and starts a new record.  Returns XDROP_E_INVALID if none was recorded. */
 int xdrop_ctx_set_timing(xdrop_ctx *ctx, int32_t on);
 int xdrop_last_timing(xdrop_ctx *ctx, float *ms, int32_t n,
                       int32_t *batches);
 
 /* Statistics of the last batch on this context (after stream sync):
  * counts of extensions finished at each tile width: counts[0..3] = 1, 2, 4,
- * 8 cells per lane, counts[4] = 0 (unused), counts[5] = workgroup tier. */
+ * 8 cells per lane (wave kernel), counts[4] = pair kernel, counts[5] =
+ * workgroup tier. */
 int xdrop_last_stats(xdrop_ctx *ctx, int64_t *counts, int32_t n_counts);
 
 /* ---------------------------------------------------------------- serving

@@ -42,6 +42,7 @@ struct xdrop_ctx {
   int32_t* counters = nullptr;
   int32_t* gen_scratch = nullptr;
   int gen_slots = 32;
+  int pair_blocks_per_cu[2] = {0, 0};
   int blocks_per_cu[2] = {0, 0};  // [alphabet]
   bool have_tuned[2] = {false, false};
   xdrop_options tuned[2];
@@ -60,7 +61,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-  size_t items, order, gen_q, bad, total;
+  size_t items, order, gen_q, esc_q, bad, total;
 };
 
 Layout layout(int32_t n_items, int32_t n_seqs) {
@@ -75,6 +76,7 @@ Layout layout(int32_t n_items, int32_t n_seqs) {
   L.items = take(ni * sizeof(ItemResult));
   L.order = take(ni * 4);
   L.gen_q = take(ni * 4);
+  L.esc_q = take(ni * 4);
   L.bad = take((size_t)std::max(n_seqs, 1));
   L.total = off;
   return L;
@@ -142,7 +144,7 @@ int fill_scoring(const xdrop_scoring* sc, Params& P) {
 
 int check_options(const xdrop_options* o) {
   if (!o) return XDROP_OK;
-  if (o->variant < 0 || o->variant > XDROP_VARIANT_PLAIN) return XDROP_E_INVALID;
+  if (o->variant < 0 || o->variant > XDROP_VARIANT_PAIR) return XDROP_E_INVALID;
   const int t = o->tile;
   if (!(t == 0 || t == 1 || t == 2 || t == 4 || t == 8))
     return XDROP_E_INVALID;
@@ -167,8 +169,12 @@ xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
     if (o->waves_per_cu) r.waves_per_cu = o->waves_per_cu;
   }
   if (!r.variant) r.variant = XDROP_VARIANT_WAVE;
+  // the pair kernel keeps no per-antidiagonal band width: a band cap runs on
+  // the wave kernel
+  if (r.variant == XDROP_VARIANT_PAIR && r.band_cap > 0)
+    r.variant = XDROP_VARIANT_WAVE;
   if (!r.tile) r.tile = 1;
-  if (!r.chunk) r.chunk = 1;
+  // chunk 0 = automatic, sized per batch in enqueue
   return r;
 }
 
@@ -207,7 +213,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   if (n_seeds == 0) return XDROP_OK;
   if (!d_seqs || !d_offsets || !d_seeds || !d_results || n_seqs == 0)
     return XDROP_E_INVALID;
-  const xdrop_options o = resolve(c, sc, opts);
+  xdrop_options o = resolve(c, sc, opts);
   const int32_t n_items = 2 * n_seeds;
   Layout L = layout(n_items, n_seqs);
   rc = ensure_workspace(c, L.total);
@@ -220,11 +226,23 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   P.items = (ItemResult*)(ws + L.items);
   P.counters = c->counters;
   P.gen_queue = (int32_t*)(ws + L.gen_q);
+  P.esc_queue = (int32_t*)(ws + L.esc_q);
   P.gen_scratch = c->gen_scratch;
   P.n_seqs = n_seqs;
   P.n_seeds = n_seeds;
   P.n_items = n_items;
   P.tile = o.tile;
+  {
+    // automatic chunk: one extension per claim while the batch fills the
+    // persistent grid at most a few times over (longest-first balance
+    // matters most there), up to 8 per claim for large batches (fewer
+    // contended atomics on the queue head)
+    const int a0 = P.alphabet;
+    if (!c->blocks_per_cu[a0]) c->blocks_per_cu[a0] = wave_blocks_per_cu(a0);
+    const int64_t waves = (int64_t)c->num_cu * c->blocks_per_cu[a0] * WPB;
+    if (!o.chunk)
+      o.chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(8, n_items / (waves * 8)));
+  }
   P.chunk = o.chunk;
   P.band_cap = o.band_cap;
   P.gen_slots = c->gen_slots;
@@ -270,6 +288,19 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     HIP_OK(launch_fill_queue(P.order, n_items, P.gen_queue, c->counters,
                              C_GEN_TAIL, st));
     if (timed) HIP_OK(hipEventRecord(ev[2], st));
+    if (timed) HIP_OK(hipEventRecord(ev[3], st));
+  } else if (o.variant == XDROP_VARIANT_PAIR) {
+    // two extensions per wave; bands wider than 32 cells are handed on to
+    // the wave kernel
+    if (!c->pair_blocks_per_cu[a]) c->pair_blocks_per_cu[a] = pair_blocks_per_cu(a);
+    const int pairs = (n_items + 1) / 2;
+    const int pgrid = std::min(c->num_cu * c->pair_blocks_per_cu[a],
+                               (pairs + WPB - 1) / WPB);
+    HIP_OK(launch_pair(P, pgrid, st));
+    if (timed) HIP_OK(hipEventRecord(ev[2], st));
+    Params Q = P;
+    Q.flags |= F_ESC;
+    HIP_OK(launch_wave(Q, persistent_grid(), st));
     if (timed) HIP_OK(hipEventRecord(ev[3], st));
   } else {
     int grid;
@@ -525,11 +556,18 @@ extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
   hipStream_t st = (hipStream_t)stream;
   const int a = sc->alphabet == XDROP_BYTE ? 1 : 0;
-  // candidates: persistent wave form (tile x chunk), the plain form (tile),
-  // the workgroup form
+  // candidates: the pair form (tile and chunk of the wave kernel that takes
+  // the extensions it hands on), the persistent wave form (tile x chunk),
+  // the plain form (tile), the workgroup form
   std::vector<xdrop_options> cand;
   const int tiles[] = {1, 2, 4, 8};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
+  for (int t : {1, 2})
+    for (int ch : {1, 4}) {
+      xdrop_options o{};
+      o.variant = XDROP_VARIANT_PAIR; o.tile = t; o.chunk = ch;
+      cand.push_back(o);
+    }
   for (int t : tiles)
     for (int ch : chunks) {
       xdrop_options o{};

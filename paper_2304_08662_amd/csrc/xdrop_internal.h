@@ -35,6 +35,7 @@ struct ItemResult {
 enum : int32_t {
   F_PLAIN = 1,      // one wave per extension, no queue
   F_ORDERED = 2,    // items[] holds the processing order
+  F_ESC = 4,        // items come from esc_queue (handed on by the pair kernel)
 };
 
 // Per-seed / per-item status values (mirror the public enum).
@@ -55,6 +56,7 @@ struct Params {
   int32_t* counters;         // queue heads and tier statistics
   const uint8_t* seq_bad;    // per-sequence check (BYTE): 2 = bad symbol
   int32_t* gen_queue;        // items handed to the general tier
+  int32_t* esc_queue;        // items handed on by the pair kernel
   int32_t* gen_scratch;      // general tier rings
   int32_t n_seqs;
   int32_t n_seeds;
@@ -77,7 +79,10 @@ enum {
   C_HEAD = 0,       // main queue head
   C_GEN_TAIL = 1,   // general queue tail
   C_GEN_HEAD = 2,   // general queue head
-  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8, -, general
+  C_ESC_TAIL = 3,   // pair kernel hand-on queue tail
+  C_ESC_HEAD = 4,   // its head (wave kernel)
+  C_PAIR_HEAD = 5,  // pair kernel queue head
+  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8, pair, general
   C_HIST = 16,      // longest-first ordering: bucket sizes
   C_CURSOR = C_HIST + 256,  // bucket write cursors
   C_COUNT = C_CURSOR + 256
@@ -102,6 +107,8 @@ hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
                              int32_t* counters, int32_t tail_slot,
                              hipStream_t s);
 hipError_t launch_wave(const Params& P, int grid, hipStream_t s);
+hipError_t launch_pair(const Params& P, int grid, hipStream_t s);
+int pair_blocks_per_cu(int alphabet);
 hipError_t launch_general(const Params& P, int grid, hipStream_t s);
 hipError_t launch_combine(const Params& P, void* out, hipStream_t s);
 int wave_blocks_per_cu(int alphabet);

@@ -1115,18 +1115,383 @@ __global__ __launch_bounds__(WAVE * WPB) void xd_wave_kernel(Params P) {
           P, S, (P.flags & F_ORDERED) ? uni(P.order[idx]) : idx, w, tab);
     return;
   }
+  // the extensions handed on by the pair kernel, or the whole batch
+  const bool esc = (P.flags & F_ESC) != 0;
+  const int n_items =
+      esc ? uni(__hip_atomic_load(P.counters + C_ESC_TAIL, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT))
+          : P.n_items;
+  if (esc && n_items == 0) return;  // nothing was handed on
   int cur = 0, end = 0;
   for (;;) {
     if (cur >= end) {
+      // (a wave that finds the queue drained leaves without touching the
+      // contended head)
+      if (esc && uni(__hip_atomic_load(P.counters + C_ESC_HEAD,
+                                       __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT)) >= n_items)
+        break;
       int c = 0;
-      if (lane_id() == 0) c = atomicAdd(P.counters + C_HEAD, P.chunk);
+      if (lane_id() == 0)
+        c = atomicAdd(P.counters + (esc ? C_ESC_HEAD : C_HEAD), P.chunk);
       cur = uni(c);
-      end = min(cur + P.chunk, P.n_items);
-      if (cur >= P.n_items) break;
+      end = min(cur + P.chunk, n_items);
+      if (cur >= n_items) break;
     }
     const int idx = cur++;
-    const int item = (P.flags & F_ORDERED) ? uni(P.order[idx]) : idx;
+    const int item = esc ? uni(P.esc_queue[idx])
+                     : (P.flags & F_ORDERED) ? uni(P.order[idx]) : idx;
     run_item<ALPHA, CMIN, CMAX>(P, S, item, w, tab);
+  }
+}
+
+// ------------------------------------------------------------------ pairs
+// Two extensions per wavefront for narrow bands.  Lanes 0-31 run extension
+// A and lanes 32-63 extension B with one cell per lane, a 32-cell window
+// each (lane 32*h + p holds window position p of half h).  Both advance
+// antidiagonal by antidiagonal in lockstep, so every vector instruction of
+// the sweep serves two extensions; the scalar bookkeeping runs on the two
+// 32-bit halves of each ballot.  As in the one-cell loop of the wave kernel:
+//  * the band bookkeeping uses the finite-lane ballots M1, M2 of the last two
+//    antidiagonals: per half lo = ctz(M1 | M2 << 1), hi = 32 - clz(M1 | M2),
+//    live-span cells 33 - (ctz + clz).  Adding min(ctz + clz, 33) keeps the
+//    sum exact after a half has died (both searches then return -1);
+//  * the top lane of each half stays -infinity (the window slides up in
+//    place when the band reaches it), so a wave rotation feeds lanes 0 and
+//    32 the -infinity of the other half's top lane;
+//  * blocks of 16 antidiagonals clear of the matrix edges skip the edge
+//    masks and clamps.
+// An extension whose band fills its 32-cell window is handed on to the wave
+// kernel, which restarts it.  The two extensions come from consecutive slots
+// of the longest-first order, so their lengths are close; the wave takes the
+// next pair once both are done.
+template <int ALPHA>
+struct PairLds {
+  WaveLds<ALPHA> h[2];
+};
+
+struct PairHalf {
+  Ext e;
+  int item;
+  int own;       // this kernel writes the result
+  int alive;     // a finite cell on one of the last two antidiagonals
+  uint32_t acc;  // this block: sum of (33 - live-span cells) per antidiagonal
+  int tbest, bd, bxa;  // last new best: V value, antidiagonal, x
+};
+
+// Maxima of v over the lanes of each half.
+__device__ __forceinline__ void half_max(int v, int& h0, int& h1) {
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
+  h0 = smax(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+  h1 = smax(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+}
+
+// Each 32-bit half of m shifted right by its own amount.
+__device__ __forceinline__ uint64_t shift_halves(uint64_t m, int s0, int s1) {
+  return (uint64_t)((uint32_t)m >> s0) |
+         ((uint64_t)((uint32_t)(m >> 32) >> s1) << 32);
+}
+
+template <int ALPHA>
+__device__ __forceinline__ void run_pair(const Params& P, const Src& S,
+                                         int item0, int item1,
+                                         PairLds<ALPHA>& L, const int* tab) {
+  constexpr uint64_t TOPS = (1ull << 31) | (1ull << 63);
+  const int lane = lane_id();
+  const int hf = lane >> 5, p = lane & 31;
+  PairHalf H[2];
+  const int items[2] = {item0, item1};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    H[h].item = items[h];
+    H[h].own = 0;
+    H[h].alive = 0;
+    H[h].acc = 0;
+    H[h].tbest = 0;
+    H[h].bd = -1;
+    H[h].bxa = 0;
+    H[h].e.base = 0;
+    H[h].e.m = H[h].e.n = 0;
+    if (items[h] < 0) continue;
+    ItemSetup st = setup_item(P, items[h]);
+    H[h].e = st.e;
+    if (st.status != S_OK || st.e.m + st.e.n == 0) {
+      ItemResult r;
+      r.best = 0; r.x = 0; r.y = 0; r.status = st.status;
+      r.cells = st.status == S_OK ? 1 : 0;
+      if (lane == 0) {
+        P.items[items[h]] = r;
+        if (st.status == S_OK) atomicAdd(P.counters + C_TIER0 + 4, 1);
+      }
+      continue;
+    }
+    H[h].own = 1;
+    H[h].alive = 1;
+    cover_a<ALPHA>(H[h].e, L.h[h], S, 30);
+    cover_b<ALPHA>(H[h].e, L.h[h], S, 0);
+  }
+  if (!H[0].alive && !H[1].alive) return;
+
+  const uint32_t* ra_l = hf ? L.h[1].ra : L.h[0].ra;
+  const uint32_t* rb_l = hf ? L.h[1].rb : L.h[0].rb;
+  const int gap = P.gap, X = smin(P.X, 1 << 29);  // see fast_interior
+  const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
+  auto code_a = [&](int idx) -> int {
+    if constexpr (ALPHA == 0) {
+      return (int)(Ring<0>::read(ra_l, idx) & 3u);
+    } else {
+      uint32_t t[1];
+      Ring<1>::read<1>(ra_l, idx, t);
+      return (int)(t[0] & 31u) << 5;
+    }
+  };
+  auto code_b = [&](int idx) -> int {
+    if constexpr (ALPHA == 0) {
+      return (int)(Ring<0>::read(rb_l, idx) & 3u);
+    } else {
+      uint32_t t[1];
+      Ring<1>::read<1>(rb_l, idx, t);
+      return (int)(t[0] & 31u);
+    }
+  };
+  int d = 1;
+  int base_l = 0;
+  int fa = code_a(p - 1);
+  int fb = code_b(d - p - 1);
+  const bool run_l = hf ? H[1].alive : H[0].alive;
+  int x = (p == 0 && run_l) ? 0 : NEG;  // antidiagonal 0: S(0,0) = 0
+  int y = NEG;
+  uint64_t m1 = (H[0].alive ? 1ull : 0ull) | (H[1].alive ? 1ull << 32 : 0ull);
+  uint64_t m2 = 0;
+  int tv_v = -gap;  // best score in the frame of antidiagonal d (T = 0)
+  int thr_v = tv_v - X;
+  int pm[2] = {0, 0}, mrel[2] = {0, 0};  // edge blocks: d - n - base, m - base
+  int pm_v = 0, mrel_v = 0;
+
+  // Antidiagonal d of both extensions from prev (d-1) and pp (d-2); pp
+  // receives d, then the target codes move one cell up and lanes 0 and 32
+  // take `in` (b[d - base - 1] of their extension).  Returns 1 when a top
+  // lane turned finite.
+  auto body = [&](auto edge_tag, int& prev, int& pp, int in) -> int {
+    constexpr bool EDGE = decltype(edge_tag)::value;
+    const uint64_t clo = m1 | (m2 << 1), chi = m1 | m2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t lo = (uint32_t)(clo >> (32 * h));
+      const uint32_t hi = (uint32_t)(chi >> (32 * h));
+      if constexpr (EDGE) {
+        const int c = (int)__builtin_ctzg(lo, 32);
+        const int z = (int)__builtin_clzg(hi, 32);
+        const int w = smax(smin(32 - z, mrel[h]) - smax(c, pm[h]) + 1, 0);
+        H[h].acc += (uint32_t)(33 - w);
+      } else {
+        const uint32_t t = (uint32_t)__builtin_ctzg(lo, -1) +
+                           (uint32_t)__builtin_clzg(hi, -1);
+        H[h].acc += t < 33u ? t : 33u;
+      }
+    }
+    const int up = __builtin_amdgcn_mov_dpp(prev, 0x13C, 0xf, 0xf, false);
+    const int dg = __builtin_amdgcn_mov_dpp(pp, 0x13C, 0xf, 0xf, false);
+    int sim;
+    if constexpr (ALPHA == 0) sim = fa == fb ? vmat : vmis;
+    else sim = tab[fa + fb];
+    const int v = max(max(up, prev), dg + sim);
+    bool f = v >= thr_v;
+    // y > n below pm, x > m above mrel (past antidiagonal m + n the range
+    // is empty: pm > mrel)
+    if constexpr (EDGE) f = f && p >= pm_v && p <= mrel_v;
+    const int vn = f ? v : NEG;
+    const uint64_t fm = ballot(f);
+    const uint64_t imp = ballot(vn > tv_v);
+    pp = vn;
+    if (imp) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t ih = (uint32_t)(imp >> (32 * h));
+        if (ih) {
+          int l = __builtin_ctz(ih);
+          int wm = __builtin_amdgcn_readlane(vn, 32 * h + l);
+          if (ih & (ih - 1)) {
+            int a0, a1;
+            half_max(vn, a0, a1);
+            wm = h ? a1 : a0;
+            l = __builtin_ctz((uint32_t)(ballot(vn == wm) >> (32 * h)));
+          }
+          H[h].tbest = wm;  // T, bx, by are formed at the end
+          H[h].bd = d;
+          H[h].bxa = H[h].e.base + l;
+          const int wv = in_vgpr(wm);
+          tv_v = hf == h ? wv : tv_v;
+          thr_v = hf == h ? wv - X : thr_v;
+        }
+      }
+    }
+    m2 = m1;
+    m1 = fm;
+    tv_v -= gap;
+    thr_v -= gap;
+    ++d;
+    if constexpr (EDGE) {
+      ++pm[0];
+      ++pm[1];
+      ++pm_v;
+    }
+    fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
+    fb = lane == 32 ? in : fb;
+    return (fm & TOPS) ? 1 : 0;
+  };
+
+  bool newest_in_y = false;
+  for (;;) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      H[h].alive = (uint32_t)((m1 | m2) >> (32 * h)) != 0;
+    if (!H[0].alive && !H[1].alive) break;
+    bool interior = true;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      pm[h] = d - H[h].e.n - H[h].e.base;
+      mrel[h] = H[h].e.m - H[h].e.base;
+      if (H[h].alive && !(pm[h] + 15 <= 0 && mrel[h] >= 31)) interior = false;
+      if (H[h].alive)
+        cover_b<ALPHA>(H[h].e, L.h[h], S, d - H[h].e.base + 15);
+    }
+    pm_v = hf ? pm[1] : pm[0];
+    mrel_v = hf ? mrel[1] : mrel[0];
+    const int d_blk = d;
+    // the 16 codes entering lanes 0 and 32 during the block
+    uint32_t qw[ALPHA == 0 ? 1 : 4];
+    if constexpr (ALPHA == 0) {
+      qw[0] = Ring<0>::read(rb_l, d - base_l);
+    } else {
+      Ring<1>::read<4>(rb_l, d - base_l, qw);
+    }
+    int st = 0;
+    auto run_block = [&](auto edge_tag) {
+#pragma unroll
+      for (int k = 0; k < 16; k += 2) {
+        const int in0 = ALPHA == 0
+            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
+            : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
+        const int in1 = ALPHA == 0
+            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
+            : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
+        st = body(edge_tag, x, y, in0);
+        if (st) { newest_in_y = true; return; }
+        st = body(edge_tag, y, x, in1);
+        if (st) { newest_in_y = false; return; }
+      }
+      newest_in_y = false;
+    };
+    if (interior) run_block(std::false_type{});
+    else run_block(std::true_type{});
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      H[h].e.W += (int64_t)33 * (d - d_blk) - (int64_t)H[h].acc;
+      H[h].acc = 0;
+    }
+    if (!st) continue;
+    // a top lane turned finite: slide that half's window up by the lanes
+    // below its lowest finite cell of d-1 and d-2, or hand the extension on
+    // when not one lane is free
+    int sl[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!((m1 >> (31 + 32 * h)) & 1)) continue;
+      const int s = __builtin_ctz((uint32_t)((m1 | m2) >> (32 * h)));
+      if (s >= 1) {
+        sl[h] = s;
+      } else {
+        if (lane == 0) {
+          const int slot = atomicAdd(P.counters + C_ESC_TAIL, 1);
+          P.esc_queue[slot] = H[h].item;
+        }
+        H[h].own = 0;
+        const uint64_t hm = 0xFFFFFFFFull << (32 * h);
+        m1 &= ~hm;
+        m2 &= ~hm;
+        x = hf == h ? NEG : x;
+        y = hf == h ? NEG : y;
+      }
+    }
+    if (sl[0] | sl[1]) {
+      const int sl_l = hf ? sl[1] : sl[0];
+      const int src = lane + sl_l;
+      const bool in = p + sl_l < 32;
+      const int nw = newest_in_y ? y : x;
+      const int od = newest_in_y ? x : y;
+      const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, nw);
+      const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, od);
+      // target codes move with their cells; stray codes at the top lanes
+      // are not used before they have moved out (see fast_interior)
+      fb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb);
+      x = in ? pn : NEG;
+      y = in ? po : NEG;
+      newest_in_y = false;
+      m1 = shift_halves(m1, sl[0], sl[1]);
+      m2 = shift_halves(m2, sl[0], sl[1]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (!sl[h]) continue;
+        H[h].e.base += sl[h];
+        cover_a<ALPHA>(H[h].e, L.h[h], S, H[h].e.base + 30);
+      }
+      base_l = hf ? H[1].e.base : H[0].e.base;
+      fa = code_a(base_l + p - 1);
+    } else if (newest_in_y) {
+      const int t = x;
+      x = y;
+      y = t;
+      newest_in_y = false;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (!H[h].own) continue;
+    ItemResult r;
+    r.status = S_OK;
+    r.cells = H[h].e.W;
+    if (H[h].bd >= 0) {
+      r.best = H[h].tbest + gap * H[h].bd;
+      r.x = H[h].bxa;
+      r.y = H[h].bd - H[h].bxa;
+    } else {
+      r.best = 0; r.x = 0; r.y = 0;
+    }
+    if (lane == 0) {
+      P.items[H[h].item] = r;
+      atomicAdd(P.counters + C_TIER0 + 4, 1);
+    }
+  }
+}
+
+// Persistent pair kernel: pairs of consecutive extensions of the (longest
+// first) order pulled from a device queue.
+template <int ALPHA>
+__global__ __launch_bounds__(WAVE * WPB) void xd_pair_kernel(Params P) {
+  __shared__ PairLds<ALPHA> lds[WPB];
+  __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
+  if constexpr (ALPHA == 1) {
+    for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
+      tab[i] = P.table[i];
+    __syncthreads();
+  }
+  const int wid = threadIdx.x >> 6;
+  PairLds<ALPHA>& L = lds[wid];
+  const Src S = make_src(P);
+  for (;;) {
+    int c = 0;
+    if (lane_id() == 0) c = atomicAdd(P.counters + C_PAIR_HEAD, 2);
+    c = uni(c);
+    if (c >= P.n_items) break;
+    const int i0 = (P.flags & F_ORDERED) ? uni(P.order[c]) : c;
+    int i1 = -1;
+    if (c + 1 < P.n_items)
+      i1 = (P.flags & F_ORDERED) ? uni(P.order[c + 1]) : c + 1;
+    run_pair<ALPHA>(P, S, i0, i1, L, tab);
   }
 }
 
@@ -1411,6 +1776,8 @@ __global__ void xd_combine_kernel(Params P, void* out_v) {
 
 template __global__ void xd_wave_kernel<0, 8>(Params);
 template __global__ void xd_wave_kernel<1, 8>(Params);
+template __global__ void xd_pair_kernel<0>(Params);
+template __global__ void xd_pair_kernel<1>(Params);
 
 }  // namespace xd
 
@@ -1476,6 +1843,29 @@ hipError_t launch_wave(const Params& P, int grid, hipStream_t s) {
     hipLaunchKernelGGL((xd_wave_kernel<1, 8>), dim3(grid), dim3(WAVE * WPB),
                        0, s, P);
   return hipGetLastError();
+}
+
+hipError_t launch_pair(const Params& P, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (P.alphabet == 0)
+    hipLaunchKernelGGL((xd_pair_kernel<0>), dim3(grid), dim3(WAVE * WPB), 0,
+                       s, P);
+  else
+    hipLaunchKernelGGL((xd_pair_kernel<1>), dim3(grid), dim3(WAVE * WPB), 0,
+                       s, P);
+  return hipGetLastError();
+}
+
+int pair_blocks_per_cu(int alphabet) {
+  int nb = 0;
+  hipError_t e =
+      alphabet == 0
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_pair_kernel<0>, WAVE * WPB, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_pair_kernel<1>, WAVE * WPB, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
 }
 
 hipError_t launch_general(const Params& P, int grid, hipStream_t s) {

@@ -33,6 +33,7 @@ VARIANT_AUTO = 0
 VARIANT_WAVE = 1
 VARIANT_WORKGROUP = 2
 VARIANT_PLAIN = 3
+VARIANT_PAIR = 4
 
 SEED_DTYPE = np.dtype([("q", "<i4"), ("t", "<i4"), ("q_pos", "<i4"),
                        ("t_pos", "<i4"), ("k", "<i4")])

@@ -168,11 +168,32 @@ def test_variants_identical(runner):
     dev = runner.upload(batch)
     for v, tile, chunk, order in [(1, 1, 1, 0), (1, 2, 3, 0), (1, 4, 8, 1),
                                   (1, 8, 64, 0), (3, 1, 1, 0), (3, 8, 1, 1),
-                                  (2, 1, 1, 0)]:
+                                  (2, 1, 1, 0), (4, 1, 1, 0), (4, 2, 4, 1),
+                                  (4, 8, 1, 0)]:
         o = xdrop.options(v, tile, chunk, 0, order)
         g = runner.run(batch, scheme, o, dev=dev)
         bad = compare(g, ref)
         assert not bad, ((v, tile, chunk, order), bad[:5])
+
+
+def test_pair_kernel_hands_on_wide_bands(runner):
+    """The default (pair) form: narrow extensions finish in the pair kernel,
+    extensions whose band outgrows 32 cells restart on the wave kernel; the
+    results equal the oracle's either way."""
+    from paper_2304_08662_amd import xdrop
+    rng = np.random.default_rng(28)
+    pairs = _fuzz_pairs(rng, 120, 4, 700, related_p=0.7)
+    # a few unrelated pairs with X -> infinity-like growth
+    batch = make_batch(pairs, 4)
+    for X in (8, 60, 2**31 - 1):
+        scheme = inputs.Scheme(4, 1, -1, -1, X)
+        ref = oracle_run(batch, scheme)
+        g = runner.run(batch, scheme, xdrop.options(variant=4))
+        assert not compare(g, ref), X
+        stats = runner.ctx.last_stats()
+        assert sum(stats) == 2 * len(batch.seeds), stats
+        if X == 8:
+            assert stats[4] > 0, stats
 
 
 def test_wide_bands_all_tiers(runner):
@@ -235,6 +256,8 @@ def test_invalid_arguments(runner):
         runner.run(batch, inputs.Scheme(4, 1, -1, -1, 5), xdrop.options(tile=3))
     with pytest.raises(xdrop.XdropError):
         runner.run(batch, inputs.Scheme(4, 1, -1, -1, -1))
+    with pytest.raises(xdrop.XdropError):
+        runner.run(batch, inputs.Scheme(4, 1, -1, -1, 5), xdrop.options(variant=5))
 
 
 def test_graph_replay(runner):
