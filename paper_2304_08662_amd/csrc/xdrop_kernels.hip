@@ -615,9 +615,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
 
   // Antidiagonal d from prev (d-1) and pp (d-2); pp receives d, then the
-  // target codes move one cell up and lane 0 takes `in`.  Returns 0 to go
-  // on, 1 when the top lane turned finite, 2 after two dead antidiagonals,
-  // 3 (edge blocks) past the last antidiagonal of the range.
+  // target codes move one cell up and lane 0 takes `in`.  Returns 1 when the
+  // top lane turned finite, after two dead antidiagonals, or (edge blocks)
+  // past the last antidiagonal of the range; 0 to go on.
   auto body = [&](auto edge_tag, int& prev, int& pp, int in) -> int {
     constexpr bool EDGE = decltype(edge_tag)::value;
     const uint64_t clo = m1 | (m2 << 1);
@@ -664,9 +664,11 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     // (before a hand-over or a slide the symbols are rebuilt, so this move
     // is harmless)
     fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
-    if ((uint32_t)(cz - 1) >= 63u) return cz == 0 ? 1 : 2;
+    // cz is 0 (top lane finite) or 64 (two dead antidiagonals) exactly when
+    // cz & 63 is 0; the reason is read from cz after the block
+    if ((cz & 63) == 0) return 1;
     if constexpr (EDGE) {
-      if (d > d_end) return 3;
+      if (d > d_end) return 1;
     }
     return 0;
   };
@@ -709,7 +711,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     else
       run_block(std::true_type{});
     if (st == 0) continue;  // 16 antidiagonals done; x holds the newest
-    if (st != 1) break;
+    if (cz != 0) break;     // two dead antidiagonals, or the end of the range
     // the top lane turned finite: slide the window up by the lanes below
     // the lowest finite cell of d and d-1 (they are -infinity on both)
     const int sl = __builtin_ctzll(m1 | m2);
@@ -759,13 +761,14 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   return r;
 }
 
-// The interior loop for C = 2 or 4 cells per lane.  Same hand-over rules as
-// for one cell per lane; the finite range of an antidiagonal, relative to
-// base, comes from its per-register ballots (cell j of lane l is window
-// position C*l + j): L = min_j C*ctz(M_j) + j, U = max_j C*(63 - clz(M_j)) + j
-// (an empty antidiagonal gives L = 64*C, U = -1).  The top cell of the
-// window (position 64*C - 1) stays -infinity, so the rotation brings
-// -infinity to lane 0.
+// The same loop for C = 2 cells per lane (cell j of lane l is window
+// position C*l + j).  The finite range of an antidiagonal, relative to base,
+// comes from its per-register ballots: L = min_j C*ctz(M_j) + j,
+// U = max_j C*(63 - clz(M_j)) + j (an empty antidiagonal gives L = 64*C,
+// U = -1).  Edge blocks mask cells outside the matrix and clamp the span;
+// the window slides up in place by whole lanes when the band reaches the top
+// cell (position 64*C - 1), which stays -infinity so that the rotation
+// brings -infinity to lane 0.
 template <int ALPHA, int C>
 __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
                                                    int (&B)[C],
@@ -774,56 +777,72 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
                                                    const int* tab,
                                                    const Params& P,
                                                    const Src& S) {
+  static_assert(C == 2, "two cells per lane");
   constexpr int TOP = 64 * C - 1;
-  constexpr int LOG2C = C == 2 ? 1 : 2;
-  const int base = e.base;
-  if (P.band_cap > 0 || e.m - base < TOP || e.d > e.n + base) return R_CONT;
+  constexpr int LOG2C = 1;
+  int base = e.base;
+  if (P.band_cap > 0) return R_CONT;
+  const int d_last = e.m + e.n - 1;
+  if (e.d > d_last) return R_CONT;
   int L1 = e.L1 > e.U1 ? 64 * C : e.L1 - base;
   int U1 = e.L1 > e.U1 ? -1 : e.U1 - base;
   int L2 = e.L2 > e.U2 ? 64 * C : e.L2 - base;
   int U2 = e.L2 > e.U2 ? -1 : e.U2 - base;
   if ((uint32_t)smax(U1, U2) >= (uint32_t)TOP) return R_CONT;
   const int d0 = e.d;
-  const int d_end = smin(e.n + base, d0 + (1 << 20));  // 32-bit sums exact
-  // every finite V lies in [-2^28, 2^28] and T's frame value tv in
-  // [0, 2^28] (value bound checked per extension), so capping X at 2^29
-  // prunes exactly the same cells and keeps tv - X above the floor
-  const int gap = P.gap, X = smin(P.X, 1 << 29);
+  const int d_end = smin(d_last, d0 + (1 << 20));  // 32-bit sums exact
+  const int gap = P.gap, X = smin(P.X, 1 << 29);  // see fast_interior
+  const int m = e.m, n = e.n;
   const int lane = lane_id();
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
-  // bare codes: cell j of lane l is x = base + C*l + j and takes
-  // a[x - 1] and b[d - x - 1]
+  // bare codes: cell j of lane l is x = base + C*l + j and takes a[x - 1]
+  // and b[d - x - 1]
   int fa[C], fb[C];
-  {
+  auto load_fa = [&]() {
     const int sa = base + lane * C - 1;
-    const int sb = d0 - base - lane * C - C;  // b index of cell C-1
     if constexpr (ALPHA == 0) {
       const uint32_t wa = Ring<0>::read(w.ra, sa);
+#pragma unroll
+      for (int j = 0; j < C; ++j) fa[j] = (int)((wa >> (2 * j)) & 3u);
+    } else {
+      uint32_t ta[1];
+      Ring<1>::read<1>(w.ra, sa, ta);
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        fa[j] = (int)((ta[0] >> (8 * j)) & 31u) << 5;
+    }
+  };
+  load_fa();
+  {
+    const int sb = d0 - base - lane * C - C;  // b index of cell C-1
+    if constexpr (ALPHA == 0) {
       const uint32_t wb = Ring<0>::read(w.rb, sb);
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
-        fa[j] = (int)((wa >> (2 * j)) & 3u);
-        fb[j] = (int)((wb >> (2 * (C - 1 - j))) & 3u);
-      }
+      for (int j = 0; j < C; ++j) fb[j] = (int)((wb >> (2 * (C - 1 - j))) & 3u);
     } else {
-      uint32_t ta[1], tb[1];
-      Ring<1>::read<1>(w.ra, sa, ta);
+      uint32_t tb[1];
       Ring<1>::read<1>(w.rb, sb, tb);
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
-        fa[j] = (int)((ta[0] >> (8 * j)) & 31u) << 5;
+      for (int j = 0; j < C; ++j)
         fb[j] = (int)((tb[0] >> (8 * (C - 1 - j))) & 31u);
-      }
     }
   }
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
   uint32_t acc = 0;         // live-span cells of the antidiagonals done
-  int tbest = 0, bd = -1, bx_rel = 0;
+  int tbest = 0, bd = -1, bxa = 0;
+  int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
 
-  // antidiagonal d from prev (d-1) and pp (d-2); pp receives d
-  auto body = [&](int (&prev)[C], int (&pp)[C], int in) -> bool {
-    acc += (uint32_t)(smax(U1, U2) - smin(L1, L2 + 1) + 2);
+  // antidiagonal d from prev (d-1) and pp (d-2); pp receives d.  Returns 1
+  // when the top cell turned finite, after two dead antidiagonals, or (edge
+  // blocks) past the last antidiagonal of the range; 0 to go on.
+  auto body = [&](auto edge_tag, int (&prev)[C], int (&pp)[C], int in) -> int {
+    constexpr bool EDGE = decltype(edge_tag)::value;
+    if constexpr (EDGE)
+      acc += (uint32_t)smax(smin(smax(U1, U2) + 1, mrel) -
+                            smax(smin(L1, L2 + 1), pm) + 1, 0);
+    else
+      acc += (uint32_t)(smax(U1, U2) - smin(L1, L2 + 1) + 2);
     const int thr = tv - X;
     int v[C];
 #pragma unroll
@@ -842,7 +861,11 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     int L0 = 64 * C, U0 = -1, lm = NEG;
 #pragma unroll
     for (int j = 0; j < C; ++j) {
-      const bool f = v[j] >= thr;
+      bool f = v[j] >= thr;
+      if constexpr (EDGE) {  // y > n below pm, x > m above mrel
+        const int pos = lane * C + j;
+        f = f && pos >= pm && pos <= mrel;
+      }
       pp[j] = f ? v[j] : NEG;
       lm = max(lm, pp[j]);
       const uint64_t fm = ballot(f);
@@ -864,28 +887,36 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       tv = wm;
       tbest = wm;  // T, bx, by are formed on hand-over
       bd = d;
-      bx_rel = (l0 << LOG2C) + __builtin_amdgcn_readlane(jf, l0);
+      bxa = base + (l0 << LOG2C) + __builtin_amdgcn_readlane(jf, l0);
     }
     L2 = L1; U2 = U1;
     L1 = L0; U1 = U0;
     tv -= gap;
     ++d;
+    if constexpr (EDGE) ++pm;
     // the target codes move one cell up; lane 0 takes `in`
     const int top = fb[C - 1];
 #pragma unroll
     for (int j = C - 1; j > 0; --j) fb[j] = fb[j - 1];
     fb[0] = __builtin_amdgcn_update_dpp(in, top, 0x138, 0xf, 0xf, false);
-    return (uint32_t)smax(U0, U2) < (uint32_t)TOP;
+    if ((uint32_t)smax(U1, U2) >= (uint32_t)TOP) return 1;
+    if constexpr (EDGE) {
+      if (d > d_end) return 1;
+    }
+    return 0;
   };
   // blocks of QB antidiagonals; the codes entering lane 0 during a block
-  // are read from the ring at its start
+  // are read from the ring at its start (blocks of 8 for byte codes keep the
+  // register footprint small)
+  constexpr int QB = ALPHA == 0 ? 16 : 8;
   int x[C], y[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) { x[j] = A[j]; y[j] = B[j]; }
   bool newest_in_y = false;
-  // (blocks of 8 for byte codes keep the register footprint small)
-  constexpr int QB = ALPHA == 0 ? 16 : 8;
-  while (d + QB - 1 <= d_end) {
+  int st = 0;
+  while (d <= d_end) {
+    pm = d - n - base;
+    mrel = m - base;
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + QB - 1);
     uint32_t qw[ALPHA == 0 ? 1 : 2];
@@ -897,30 +928,65 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
 #pragma unroll
     for (int i = 0; i < (ALPHA == 0 ? 1 : 2); ++i)
       qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+    auto run_block = [&](auto edge_tag) {
 #pragma unroll
-    for (int k = 0; k < QB; k += 2) {
-      const int in0 = ALPHA == 0
-          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
-          : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
-      const int in1 = ALPHA == 0
-          ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
-          : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
-      if (!body(x, y, in0)) { newest_in_y = true; goto done; }
-      if (!body(y, x, in1)) { newest_in_y = false; goto done; }
+      for (int k = 0; k < QB; k += 2) {
+        const int in0 = ALPHA == 0
+            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
+            : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
+        const int in1 = ALPHA == 0
+            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
+            : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
+        st = body(edge_tag, x, y, in0);
+        if (st) { newest_in_y = true; return; }
+        st = body(edge_tag, y, x, in1);
+        if (st) { newest_in_y = false; return; }
+      }
+    };
+    if (pm + QB - 1 <= 0 && mrel >= TOP && d + QB - 1 <= d_end)
+      run_block(std::false_type{});
+    else
+      run_block(std::true_type{});
+    if (st == 0) continue;  // QB antidiagonals done; x holds the newest
+    if (U1 != TOP) break;   // two dead antidiagonals, or the end of the range
+    // the top cell turned finite: slide the window up by the whole lanes
+    // below the lowest finite cell of d and d-1
+    const int sl = smin(L1, L2) >> LOG2C;
+    if (sl < 1) break;
+    const int src = lane + sl;
+    const bool in = src < 64;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int nw = newest_in_y ? y[j] : x[j];
+      const int od = newest_in_y ? x[j] : y[j];
+      const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, nw);
+      const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, od);
+      // target codes move with their cells; stray codes at the top lanes
+      // are not used before they have moved out (see fast_interior)
+      fb[j] = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb[j]);
+      x[j] = in ? pn : NEG;
+      y[j] = in ? po : NEG;
     }
+    newest_in_y = false;
+    st = 0;
+    L1 -= sl << LOG2C; U1 -= sl << LOG2C;
+    L2 -= sl << LOG2C; U2 -= sl << LOG2C;
+    base += sl << LOG2C;
+    cover_a<ALPHA>(e, w, S, base + TOP - 1);
+    load_fa();
   }
-done:
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     A[j] = newest_in_y ? y[j] : x[j];
     B[j] = newest_in_y ? x[j] : y[j];
   }
+  e.base = base;
   e.d = d;
   e.W += (int64_t)acc;
   if (bd >= 0) {
     e.T = tbest + gap * bd;
-    e.bx = base + bx_rel;
-    e.by = bd - e.bx;
+    e.bx = bxa;
+    e.by = bd - bxa;
   }
   e.L1 = U1 < 0 ? DEAD_L : base + L1;
   e.U1 = U1 < 0 ? DEAD_U : base + U1;
