@@ -537,6 +537,12 @@ __device__ __forceinline__ int step(Ext& e, int (&A)[C], int (&B)[C],
 }
 
 // ------------------------------------------------------------------ interior
+// Hide a value's origin from the optimiser (no instruction is emitted), so
+// that it cannot turn the operations that follow into longer forms: a
+// scalar (s) or vector (v) register.
+__device__ __forceinline__ void opaque_s(uint32_t& v) { asm("" : "+s"(v)); }
+__device__ __forceinline__ void opaque_v(int& v) { asm("" : "+v"(v)); }
+
 // A value that the compiler keeps in a VGPR (a loop-invariant operand of a
 // per-lane select, which may not read two SGPRs).
 __device__ __forceinline__ int in_vgpr(int v) {
@@ -550,16 +556,19 @@ __device__ __forceinline__ int in_vgpr(int v) {
 //   hi_d = min(64 - clz(M1 | M2), m - base),
 // where the clamps matter only near the matrix edges; blocks of 16
 // antidiagonals that stay clear of both edges skip them and the per-lane
-// edge masks.  The top lane stays -infinity in this loop, so the neighbour
-// exchange is a wave rotation that brings -infinity to lane 0; when the band
-// reaches the top lane the window slides up in place by the dead lanes below
-// the band.  Symbols are bare codes (DNA: the 2-bit code; bytes: the target
-// code and 32 x the query code, a table row); the 16 codes that enter lane 0
-// during a block are read from the ring at its start.  The loop computes
-// antidiagonals up to m + n - 1 and hands over to the generic step (state as
-// that step expects) at the last one, after two dead antidiagonals, or when
-// the band fills the window; R_ESC when the window can neither slide nor
-// stay.
+// edge masks.  The two top lanes stay -infinity at the start of every pair
+// of antidiagonals (the band grows by at most one lane per antidiagonal, so
+// the top lane is still -infinity one antidiagonal later): the neighbour
+// exchange is then a wave rotation that brings -infinity to lane 0, and the
+// band is tested against the top only every second antidiagonal.  When the
+// band reaches lane 62 the window slides up in place by the dead lanes below
+// the band.  DNA scores come from a per-block match word (bit 2k of lane l:
+// the codes of cell base + l agree on antidiagonal d + k); byte codes move
+// one cell up per antidiagonal, lane 0 taking the next queued code, and
+// index the score table.  The loop computes antidiagonals up to m + n - 1
+// and hands over to the generic step (state as that step expects) at the
+// last one, after two dead antidiagonals, or when the band fills the window;
+// R_ESC when the window can neither slide nor stay.
 template <int ALPHA>
 __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
                                              Syms<ALPHA, 1>& sy,
@@ -574,13 +583,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
                 : (1ull << (e.L1 - base)) | (1ull << (e.U1 - base));
   uint64_t m2 = e.L2 > e.U2 ? 0
                 : (1ull << (e.L2 - base)) | (1ull << (e.U2 - base));
-  {
-    const uint64_t chi = m1 | m2;
-    if (chi == 0 || (chi >> 63)) return R_CONT;
-  }
-  // leading zeros of M1 | M2: 64 when both antidiagonals are dead, 0 when
-  // the top lane holds a finite cell (the two cases the loop acts on)
-  int cz = (int)__builtin_clzg(m1 | m2, 64);
+  if ((m1 | m2) == 0) return R_CONT;
+  // leading zeros of M1 | M2 (never both zero inside the loop)
+  int cz = (int)__builtin_clzll(m1 | m2);
   const int d0 = e.d;
   const int d_end = smin(d_last, d0 + (1 << 20));  // 32-bit sums exact
   // every finite V lies in [-2^28, 2^28] and T's frame value tv in
@@ -590,20 +595,21 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   const int m = e.m, n = e.n;
   const int lane = lane_id();
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
-  int fa, fb;
+  // DNA: the query code of each lane copied into all 16 code slots of a
+  // word; bytes: 32 x the query code (a table row) and the target code
+  uint32_t fa = 0;
+  int fb = 0;
   auto load_fa = [&]() {
     if constexpr (ALPHA == 0) {
-      fa = (int)(Ring<0>::read(w.ra, base + lane - 1) & 3u);
+      fa = (Ring<0>::read(w.ra, base + lane - 1) & 3u) * 0x55555555u;
     } else {
       uint32_t t[1];
       Ring<1>::read<1>(w.ra, base + lane - 1, t);
-      fa = (int)(t[0] & 31u) << 5;
+      fa = (t[0] & 31u) << 5;
     }
   };
   load_fa();
-  if constexpr (ALPHA == 0) {
-    fb = (int)(Ring<0>::read(w.rb, d0 - base - lane - 1) & 3u);
-  } else {
+  if constexpr (ALPHA == 1) {
     uint32_t t[1];
     Ring<1>::read<1>(w.rb, d0 - base - lane - 1, t);
     fb = (int)(t[0] & 31u);
@@ -613,132 +619,150 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   uint32_t acc = 0;         // sum over d of (65 - live-span cells)
   int tbest = 0, bd = -1, bxa = 0;  // last new best: V value, d, x
   int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
+  int rem = 0;              // edge blocks: d_end - d
+  uint32_t mw = 0;          // DNA: match word of the block
+  uint32_t qw[4] = {0, 0, 0, 0};  // bytes: codes entering lane 0
 
-  // Antidiagonal d from prev (d-1) and pp (d-2); pp receives d, then the
-  // target codes move one cell up and lane 0 takes `in`.  Returns 1 when the
-  // top lane turned finite, after two dead antidiagonals, or (edge blocks)
-  // past the last antidiagonal of the range; 0 to go on.
-  auto body = [&](auto edge_tag, int& prev, int& pp, int in) -> int {
+  // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2); pp receives d + k.
+  // True after two dead antidiagonals, (odd k only) when the band reached
+  // lane 62, or (edge blocks) at the last antidiagonal of the range; the
+  // reason is read from the masks and d after the block.  d itself moves
+  // once per block.
+  auto body = [&](auto edge_tag, int& prev, int& pp, int k) -> bool {
     constexpr bool EDGE = decltype(edge_tag)::value;
     const uint64_t clo = m1 | (m2 << 1);
     if constexpr (EDGE) {
-      const int lo = smax(__builtin_ctzll(clo), pm);
+      const int lo = smax(__builtin_ctzll(clo), pm + k);
       const int hi = smin(64 - cz, mrel);
       acc += (uint32_t)(65 - smax(hi - lo + 1, 0));
     } else {
       acc += (uint32_t)(__builtin_ctzll(clo) + cz);
     }
     const int thr = tv - X;
-    const int up = __builtin_amdgcn_mov_dpp(prev, 0x13C, 0xf, 0xf, false);
-    const int dg = __builtin_amdgcn_mov_dpp(pp, 0x13C, 0xf, 0xf, false);
     int sim;
-    if constexpr (ALPHA == 0) sim = fa == fb ? vmat : vmis;
-    else sim = tab[fa + fb];
+    if constexpr (ALPHA == 0) {
+      int t = __builtin_amdgcn_sbfe((int)mw, 2 * k, 1);  // -1: match
+      opaque_v(t);  // keeps the bit select one v_bfi (not compare + select)
+      sim = (t & vmat) | (~t & vmis);
+    } else {
+      sim = tab[(int)fa + fb];
+    }
+    // (every lane of a wave rotation has a source, so bound_ctrl changes
+    // nothing; it lets the compiler fold the move into its user)
+    const int up = __builtin_amdgcn_update_dpp(0, prev, 0x13C, 0xf, 0xf, true);
+    const int dg = __builtin_amdgcn_update_dpp(0, pp, 0x13C, 0xf, 0xf, true);
     const int v = max(max(up, prev), dg + sim);
-    bool f = v >= thr;
+    uint64_t fm = ballot(v >= thr);
     if constexpr (EDGE)  // y > n below pm, x > m above mrel
-      f = f && (uint32_t)(lane - pm) <= (uint32_t)(mrel - pm);
-    const int vn = f ? v : NEG;
-    const uint64_t fm = ballot(f);
-    const uint64_t imp = ballot(vn > tv);
+      fm &= ballot((uint32_t)(lane - (pm + k)) <= (uint32_t)(mrel - (pm + k)));
+    const int vn = __builtin_amdgcn_inverse_ballot_w64(fm) ? v : NEG;
+    // away from the edges a cell with v > tv >= thr is finite, so the
+    // improvement test need not wait for the select
+    const int vi = EDGE ? vn : v;
+    const uint64_t imp = ballot(vi > tv);
     pp = vn;
-    if (imp) {
+    if (__builtin_expect(imp != 0, 0)) {
       // usually a single lane beats T: its value is the new best
       int l0 = __builtin_ctzll(imp);
-      int wm = __builtin_amdgcn_readlane(vn, l0);
+      int wm = __builtin_amdgcn_readlane(vi, l0);
       if (imp & (imp - 1)) {
-        wm = uni(wave_max(vn));
-        l0 = __builtin_ctzll(ballot(vn == wm));
+        wm = uni(wave_max(vi));
+        l0 = __builtin_ctzll(ballot(vi == wm));
       }
       tv = wm;
       tbest = wm;  // T, bx, by are formed on hand-over
-      bd = d;
+      bd = d + k;
       bxa = base + l0;
     }
     m2 = m1;
     m1 = fm;
-    cz = (int)__builtin_clzg(fm | m2, 64);
     tv -= gap;
-    ++d;
-    if constexpr (EDGE) ++pm;
-    // (before a hand-over or a slide the symbols are rebuilt, so this move
-    // is harmless)
-    fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
-    // cz is 0 (top lane finite) or 64 (two dead antidiagonals) exactly when
-    // cz & 63 is 0; the reason is read from cz after the block
-    if ((cz & 63) == 0) return 1;
-    if constexpr (EDGE) {
-      if (d > d_end) return 1;
+    if constexpr (ALPHA == 1) {
+      // the target codes move one cell up; lane 0 takes the next one
+      const int in = (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
+      fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
     }
-    return 0;
+    const uint64_t o = m1 | m2;
+    if (o == 0) return true;
+    cz = (int)__builtin_clzll(o);
+    if (k & 1) {
+      // lane 62 or 63 finite; tested on the high word, since a 64-bit
+      // compare would run on the vector unit
+      uint32_t hw = (uint32_t)(o >> 32);
+      opaque_s(hw);
+      if (hw >= (1u << 30)) return true;
+    }
+    if constexpr (EDGE) {
+      if (k >= rem) return true;  // d + k is d_end
+    }
+    return false;
   };
 
   // x holds d-1 and y holds d-2 at the start of a block
   int x = A[0], y = B[0];
-  bool newest_in_y = false;
-  int st = 0;
   while (d <= d_end) {
+    if (cz < 2) {
+      // the band reached lane 62: slide the window up by the lanes below
+      // the lowest finite cell of d-1 and d-2 (they are -infinity on both)
+      const int sl = __builtin_ctzll(m1 | m2);
+      if (cz + sl < 2) break;
+      const int src = lane + sl;
+      const bool in = src < 64;
+      const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
+      const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y);
+      if constexpr (ALPHA == 1) {
+        // target codes move with their cells; the top lanes receive stray
+        // codes, which no finite cell uses before they have moved out (a
+        // cell there has a -infinity diagonal predecessor until the band
+        // reaches it)
+        fb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb);
+      }
+      x = in ? pn : NEG;
+      y = in ? po : NEG;
+      m1 >>= sl;
+      m2 >>= sl;
+      cz += sl;
+      base += sl;
+      cover_a<ALPHA>(e, w, S, base + 62);
+      load_fa();
+    }
     pm = d - n - base;
     mrel = m - base;
+    rem = d_end - d;
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + 15);
-    uint32_t qw[ALPHA == 0 ? 1 : 4];
     if constexpr (ALPHA == 0) {
-      qw[0] = Ring<0>::read(w.rb, e0);
+      // codes of b[e0 - lane - 1 + k], k < 16, against the lane's query code
+      const uint32_t xw = Ring<0>::read(w.rb, e0 - lane - 1) ^ fa;
+      mw = ~(xw | (xw >> 1)) & 0x55555555u;
     } else {
       Ring<1>::read<4>(w.rb, e0, qw);
-    }
 #pragma unroll
-    for (int i = 0; i < (ALPHA == 0 ? 1 : 4); ++i)
-      qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+      for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+    }
+    int nk = 16;  // antidiagonals computed by the block
+    bool newest_in_y = false;
     auto run_block = [&](auto edge_tag) {
 #pragma unroll
       for (int k = 0; k < 16; k += 2) {
-        const int in0 = ALPHA == 0
-            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
-            : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
-        const int in1 = ALPHA == 0
-            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
-            : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
-        st = body(edge_tag, x, y, in0);
-        if (st) { newest_in_y = true; return; }
-        st = body(edge_tag, y, x, in1);
-        if (st) { newest_in_y = false; return; }
+        if (body(edge_tag, x, y, k)) { nk = k + 1; newest_in_y = true; return; }
+        if (body(edge_tag, y, x, k + 1)) { nk = k + 2; return; }
       }
     };
-    if (pm + 15 <= 0 && mrel >= 63 && d + 15 <= d_end)
+    if (pm + 15 <= 0 && mrel >= 63 && rem >= 15)
       run_block(std::false_type{});
     else
       run_block(std::true_type{});
-    if (st == 0) continue;  // 16 antidiagonals done; x holds the newest
-    if (cz != 0) break;     // two dead antidiagonals, or the end of the range
-    // the top lane turned finite: slide the window up by the lanes below
-    // the lowest finite cell of d and d-1 (they are -infinity on both)
-    const int sl = __builtin_ctzll(m1 | m2);
-    if (sl < 1) break;
-    const int src = lane + sl;
-    const bool in = src < 64;
-    const int nw = newest_in_y ? y : x;
-    const int od = newest_in_y ? x : y;
-    const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, nw);
-    const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, od);
-    // target codes move with their cells; the top lanes receive stray codes,
-    // which no finite cell uses before they have moved out (a cell there has
-    // a -infinity diagonal predecessor until the band reaches it)
-    fb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb);
-    x = in ? pn : NEG;
-    y = in ? po : NEG;
-    newest_in_y = false;
-    st = 0;
-    m1 >>= sl;
-    m2 >>= sl;
-    cz = (int)__builtin_clzg(m1 | m2, 64);
-    base += sl;
-    cover_a<ALPHA>(e, w, S, base + 62);
-    load_fa();
+    d += nk;
+    if (newest_in_y) {
+      const int t = x;
+      x = y;
+      y = t;
+    }
+    if ((m1 | m2) == 0) break;  // two dead antidiagonals
   }
-  A[0] = newest_in_y ? y : x;
-  B[0] = newest_in_y ? x : y;
+  A[0] = x;
+  B[0] = y;
 
   e.base = base;
   e.d = d;
