@@ -228,8 +228,6 @@ def main():
                  "chunk": best.chunk}
         log(f"tuned {tuned}")
         opts = None  # automatic: the context now holds the tuned choice
-    ctx.set_timing(True)
-
     def step():
         ctx.extend_batch(d_seqs, d_offs, d_seeds, sc, res, opts,
                          stream=stream)
@@ -237,8 +235,9 @@ def main():
     for _ in range(args.warmup):
         step()
     stream.synchronize()
-    ctx.last_timing()  # discard the warm-up record
     log("warm")
+    # the timed steps carry no per-phase events (each event record is a
+    # marker packet on the stream and costs microseconds of its own)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -256,7 +255,14 @@ def main():
     live = int(got["cells"].sum())
     cells = batch.gcups_cells()
     gcups = cells / (ms_step / 1e3) / 1e9
+    # per-phase durations (HIP events on the launch stream around each
+    # kernel of the sequence) from a second run of the same steps
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    stream.synchronize()
     phase_sum, nb = ctx.last_timing()
+    ctx.set_timing(False)
     assert nb == args.steps
     phase = np.array(phase_sum) / nb
     # (1) the first extension kernel: the pair kernel in the default form,

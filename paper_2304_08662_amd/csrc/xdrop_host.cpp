@@ -178,6 +178,10 @@ xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
   return r;
 }
 
+void drop_graphs(xdrop_ctx* c);
+
+// Device buffers of the launch sequence.  Graphs captured earlier hold the
+// old workspace address, so a move drops them.
 int ensure_workspace(xdrop_ctx* c, size_t bytes) {
   if (!c->counters) {
     HIP_OK(hipMalloc(&c->counters, C_COUNT * sizeof(int32_t)));
@@ -188,6 +192,7 @@ int ensure_workspace(xdrop_ctx* c, size_t bytes) {
                      (size_t)c->gen_slots * 3 * GEN_CAP * sizeof(int32_t)));
   }
   if (bytes > c->ws_bytes) {
+    drop_graphs(c);
     if (c->ws) HIP_OK(hipFree(c->ws));
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -498,8 +503,7 @@ extern "C" int xdrop_extend_batch_graph(
   }
   // everything that allocates or queries happens before the capture
   Layout L = layout(2 * n_seeds, n_seqs);
-  if (L.total > c->ws_bytes) drop_graphs(c);  // the workspace moves
-  rc = ensure_workspace(c, L.total);
+  rc = ensure_workspace(c, L.total);  // (drops the graphs if it moves)
   if (rc != XDROP_OK) return rc;
   for (int a = 0; a < 2; ++a)
     if (!c->blocks_per_cu[a]) c->blocks_per_cu[a] = wave_blocks_per_cu(a);

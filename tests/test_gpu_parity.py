@@ -177,7 +177,7 @@ def test_variants_identical(runner):
 
 
 def test_pair_kernel_hands_on_wide_bands(runner):
-    """The default (pair) form: narrow extensions finish in the pair kernel,
+    """The pair form: narrow extensions finish in the pair kernel,
     extensions whose band outgrows 32 cells restart on the wave kernel; the
     results equal the oracle's either way."""
     from paper_2304_08662_amd import xdrop
@@ -274,3 +274,23 @@ def test_graph_replay(runner):
         torch.zeros(1000, device="cuda").sum().item()
         g2 = runner.run(batch, scheme, dev=dev)
         assert not compare(g2, ref)
+
+
+def test_graph_after_workspace_growth():
+    """A graph recorded for a small batch is not replayed after a larger
+    batch has moved the workspace: the library records it again."""
+    from paper_2304_08662_amd import xdrop
+    r = Runner()  # a context of its own, so that its workspace starts small
+    try:
+        rng = np.random.default_rng(33)
+        small = make_batch(_fuzz_pairs(rng, 40, 4, 300), 4)
+        big = make_batch(_fuzz_pairs(rng, 3000, 4, 300), 4)
+        scheme = inputs.Scheme(4, 1, -1, -1, 20)
+        ref_s = oracle_run(small, scheme)
+        ref_b = oracle_run(big, scheme)
+        dev_s = r.upload(small)
+        assert not compare(r.run(small, scheme, graph=True, dev=dev_s), ref_s)
+        assert not compare(r.run(big, scheme), ref_b)  # the workspace grows
+        assert not compare(r.run(small, scheme, graph=True, dev=dev_s), ref_s)
+    finally:
+        r.ctx.close()
