@@ -623,14 +623,16 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   uint32_t mw = 0;          // DNA: match word of the block
   uint32_t qw[4] = {0, 0, 0, 0};  // bytes: codes entering lane 0
 
-  // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2); pp receives d + k.
-  // True after two dead antidiagonals, (odd k only) when the band reached
-  // lane 62, or (edge blocks) at the last antidiagonal of the range; the
-  // reason is read from the masks and d after the block.  d itself moves
-  // once per block.
-  auto body = [&](auto edge_tag, int& prev, int& pp, int k) -> bool {
+  // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
+  // finite-lane masks mp and mpp; pp and mpp receive d + k (the two
+  // antidiagonals and their masks swap roles every step).  True after two
+  // dead antidiagonals, (odd k only) when the band reached lane 62, or (edge
+  // blocks) at the last antidiagonal of the range; the reason is read from
+  // the masks and d after the block.  d itself moves once per block.
+  auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
+                  uint64_t& mpp, int k) -> bool {
     constexpr bool EDGE = decltype(edge_tag)::value;
-    const uint64_t clo = m1 | (m2 << 1);
+    const uint64_t clo = mp | (mpp << 1);
     if constexpr (EDGE) {
       const int lo = smax(__builtin_ctzll(clo), pm + k);
       const int hi = smin(64 - cz, mrel);
@@ -674,15 +676,14 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       bd = d + k;
       bxa = base + l0;
     }
-    m2 = m1;
-    m1 = fm;
+    mpp = fm;
     tv -= gap;
     if constexpr (ALPHA == 1) {
       // the target codes move one cell up; lane 0 takes the next one
       const int in = (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
       fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
     }
-    const uint64_t o = m1 | m2;
+    const uint64_t o = mp | fm;
     if (o == 0) return true;
     cz = (int)__builtin_clzll(o);
     if (k & 1) {
@@ -698,7 +699,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     return false;
   };
 
-  // x holds d-1 and y holds d-2 at the start of a block
+  // x (mask m1) holds d-1 and y (mask m2) holds d-2 at the start of a block
   int x = A[0], y = B[0];
   while (d <= d_end) {
     if (cz < 2) {
@@ -745,8 +746,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     auto run_block = [&](auto edge_tag) {
 #pragma unroll
       for (int k = 0; k < 16; k += 2) {
-        if (body(edge_tag, x, y, k)) { nk = k + 1; newest_in_y = true; return; }
-        if (body(edge_tag, y, x, k + 1)) { nk = k + 2; return; }
+        if (body(edge_tag, x, y, m1, m2, k)) {
+          nk = k + 1; newest_in_y = true; return;
+        }
+        if (body(edge_tag, y, x, m2, m1, k + 1)) { nk = k + 2; return; }
       }
     };
     if (pm + 15 <= 0 && mrel >= 63 && rem >= 15)
@@ -759,6 +762,12 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       x = y;
       y = t;
     }
+    // the masks again from the cells (a cell is finite exactly when it is not
+    // -infinity): the block's many ends then need not carry them, which
+    // would cost register moves on every block
+    m1 = ballot(x != NEG);
+    m2 = ballot(y != NEG);
+    cz = (int)__builtin_clzg(m1 | m2, 64);
     if ((m1 | m2) == 0) break;  // two dead antidiagonals
   }
   A[0] = x;
