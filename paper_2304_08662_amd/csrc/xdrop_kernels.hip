@@ -62,6 +62,21 @@ __device__ __forceinline__ int wave_max(int v) {
   return max(max(r0, r1), max(r2, r3));
 }
 
+// v_writelane_b32: lane `lane` of `old` takes the uniform value `val`.  This
+// compiler has no source-level builtin for it; the declaration binds the
+// function to the target intrinsic's own name.
+extern "C" __device__ int xd_writelane_i32(int val, int lane, int old) __asm(
+    "llvm.amdgcn.writelane.i32");
+
+// Sum of lanes 0..31 (a uniform value).
+__device__ __forceinline__ int sum_lanes_0_31(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16);
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) {
   return __ballot(p);
 }
@@ -621,6 +636,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
   int rem = 0;              // edge blocks: d_end - d
   uint32_t mw = 0;          // DNA: match word of the block
+  // finite-lane masks of the block's antidiagonals for the live-span count,
+  // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
+  // the two antidiagonals before the block, lane k + 2 the block's k-th
+  int ml = 0, mh = 0;
   uint32_t qw[4] = {0, 0, 0, 0};  // bytes: codes entering lane 0
 
   // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
@@ -632,14 +651,6 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
                   uint64_t& mpp, int k) -> bool {
     constexpr bool EDGE = decltype(edge_tag)::value;
-    const uint64_t clo = mp | (mpp << 1);
-    if constexpr (EDGE) {
-      const int lo = smax(__builtin_ctzll(clo), pm + k);
-      const int hi = smin(64 - cz, mrel);
-      acc += (uint32_t)(65 - smax(hi - lo + 1, 0));
-    } else {
-      acc += (uint32_t)(__builtin_ctzll(clo) + cz);
-    }
     const int thr = tv - X;
     int sim;
     if constexpr (ALPHA == 0) {
@@ -677,6 +688,8 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       bxa = base + l0;
     }
     mpp = fm;
+    ml = xd_writelane_i32((int)(uint32_t)fm, k + 2, ml);
+    mh = xd_writelane_i32((int)(uint32_t)(fm >> 32), k + 2, mh);
     tv -= gap;
     if constexpr (ALPHA == 1) {
       // the target codes move one cell up; lane 0 takes the next one
@@ -685,7 +698,6 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     }
     const uint64_t o = mp | fm;
     if (o == 0) return true;
-    cz = (int)__builtin_clzll(o);
     if (k & 1) {
       // lane 62 or 63 finite; tested on the high word, since a 64-bit
       // compare would run on the vector unit
@@ -741,6 +753,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
 #pragma unroll
       for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)in_vgpr((int)qw[i]);
     }
+    ml = xd_writelane_i32((int)(uint32_t)m2, 0, ml);
+    mh = xd_writelane_i32((int)(uint32_t)(m2 >> 32), 0, mh);
+    ml = xd_writelane_i32((int)(uint32_t)m1, 1, ml);
+    mh = xd_writelane_i32((int)(uint32_t)(m1 >> 32), 1, mh);
     int nk = 16;  // antidiagonals computed by the block
     bool newest_in_y = false;
     auto run_block = [&](auto edge_tag) {
@@ -756,6 +772,26 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       run_block(std::false_type{});
     else
       run_block(std::true_type{});
+    {
+      // live-span cells of the block's antidiagonals, one per lane k + 2,
+      // from the masks of the two antidiagonals before each (lanes k + 1 and
+      // k): 65 - |[max(lo, d - n - base), min(hi, m - base)]| with
+      // lo = ctz(M1 | M2 << 1), hi = 64 - clz(M1 | M2) (never both masks
+      // zero, and M2 never holds lane 63, so neither search comes up empty)
+      const uint32_t al = (uint32_t)wave_shr1(ml, 0), ah = (uint32_t)wave_shr1(mh, 0);
+      const uint32_t bl = (uint32_t)wave_shr1((int)al, 0), bh = (uint32_t)wave_shr1((int)ah, 0);
+      const uint32_t cl = al | (bl << 1);
+      const uint32_t ch = ah | __builtin_amdgcn_alignbit(bh, bl, 31);
+      const uint32_t ctz = min((uint32_t)__builtin_ctzg(cl, -1),
+                               (uint32_t)__builtin_ctzg(ch, -1) | 32u);
+      const uint32_t clz = min((uint32_t)__builtin_clzg(ah | bh, -1),
+                               (uint32_t)__builtin_clzg(al | bl, -1) | 32u);
+      const int kk = lane - 2;
+      const int lo = max((int)ctz, pm + kk);
+      const int hi = min(64 - (int)clz, mrel);
+      const int cnt = (kk >= 0 && kk < nk) ? 65 - max(hi - lo + 1, 0) : 0;
+      acc += (uint32_t)sum_lanes_0_31(cnt);
+    }
     d += nk;
     if (newest_in_y) {
       const int t = x;
