@@ -644,10 +644,12 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
 
   // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
   // finite-lane masks mp and mpp; pp and mpp receive d + k (the two
-  // antidiagonals and their masks swap roles every step).  True after two
-  // dead antidiagonals, (odd k only) when the band reached lane 62, or (edge
+  // antidiagonals and their masks swap roles every step).  True (odd k only)
+  // after two dead antidiagonals or when the band reached lane 62, or (edge
   // blocks) at the last antidiagonal of the range; the reason is read from
-  // the masks and d after the block.  d itself moves once per block.
+  // the masks and d after the block.  (Two dead antidiagonals at an even k
+  // are followed by one more, dead as well, that adds no live-span cell.)
+  // d itself moves once per block.
   auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
                   uint64_t& mpp, int k) -> bool {
     constexpr bool EDGE = decltype(edge_tag)::value;
@@ -696,9 +698,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       const int in = (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
       fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
     }
-    const uint64_t o = mp | fm;
-    if (o == 0) return true;
     if (k & 1) {
+      const uint64_t o = mp | fm;
+      if (o == 0) return true;
       // lane 62 or 63 finite; tested on the high word, since a 64-bit
       // compare would run on the vector unit
       uint32_t hw = (uint32_t)(o >> 32);
@@ -776,8 +778,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       // live-span cells of the block's antidiagonals, one per lane k + 2,
       // from the masks of the two antidiagonals before each (lanes k + 1 and
       // k): 65 - |[max(lo, d - n - base), min(hi, m - base)]| with
-      // lo = ctz(M1 | M2 << 1), hi = 64 - clz(M1 | M2) (never both masks
-      // zero, and M2 never holds lane 63, so neither search comes up empty)
+      // lo = ctz(M1 | M2 << 1), hi = 64 - clz(M1 | M2) (M2 never holds lane
+      // 63, so neither search comes up empty unless both masks are zero: an
+      // antidiagonal after two dead ones, with no live-span cell)
       const uint32_t al = (uint32_t)wave_shr1(ml, 0), ah = (uint32_t)wave_shr1(mh, 0);
       const uint32_t bl = (uint32_t)wave_shr1((int)al, 0), bh = (uint32_t)wave_shr1((int)ah, 0);
       const uint32_t cl = al | (bl << 1);
@@ -789,7 +792,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       const int kk = lane - 2;
       const int lo = max((int)ctz, pm + kk);
       const int hi = min(64 - (int)clz, mrel);
-      const int cnt = (kk >= 0 && kk < nk) ? 65 - max(hi - lo + 1, 0) : 0;
+      const bool live = (al | ah | bl | bh) != 0;
+      const int cnt = (kk >= 0 && kk < nk)
+                          ? (live ? 65 - max(hi - lo + 1, 0) : 65) : 0;
       acc += (uint32_t)sum_lanes_0_31(cnt);
     }
     d += nk;
