@@ -836,13 +836,15 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
 }
 
 // The same loop for C = 2 cells per lane (cell j of lane l is window
-// position C*l + j).  The finite range of an antidiagonal, relative to base,
-// comes from its per-register ballots: L = min_j C*ctz(M_j) + j,
-// U = max_j C*(63 - clz(M_j)) + j (an empty antidiagonal gives L = 64*C,
-// U = -1).  Edge blocks mask cells outside the matrix and clamp the span;
-// the window slides up in place by whole lanes when the band reaches the top
-// cell (position 64*C - 1), which stays -infinity so that the rotation
-// brings -infinity to lane 0.
+// position 2l + j), with one finite-lane mask per register (M_j: the lanes
+// whose cell j is finite).  The top two lanes (positions 124..127) stay
+// -infinity at the start of every pair of antidiagonals, so the rotation
+// brings -infinity to cell 0 of lane 0 and the band is tested against the
+// top (and for two dead antidiagonals) only every second antidiagonal; the
+// window slides up in place by whole lanes.  Edge blocks mask cells outside
+// the matrix.  Live-span cells are counted per block on the vector unit from
+// the masks kept in lanes (as in the one-cell loop), with
+//   L = min_j 2 ctz(M_j) + j,  U = max_j 2 (63 - clz(M_j)) + j.
 template <int ALPHA, int C>
 __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
                                                    int (&B)[C],
@@ -852,24 +854,22 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
                                                    const Params& P,
                                                    const Src& S) {
   static_assert(C == 2, "two cells per lane");
-  constexpr int TOP = 64 * C - 1;
-  constexpr int LOG2C = 1;
   int base = e.base;
   if (P.band_cap > 0) return R_CONT;
   const int d_last = e.m + e.n - 1;
   if (e.d > d_last) return R_CONT;
-  int L1 = e.L1 > e.U1 ? 64 * C : e.L1 - base;
-  int U1 = e.L1 > e.U1 ? -1 : e.U1 - base;
-  int L2 = e.L2 > e.U2 ? 64 * C : e.L2 - base;
-  int U2 = e.L2 > e.U2 ? -1 : e.U2 - base;
-  if ((uint32_t)smax(U1, U2) >= (uint32_t)TOP) return R_CONT;
+  const int lane = lane_id();
+  // finite-lane masks of d-1 (x) and d-2 (y), from the cells (a cell is
+  // finite exactly when it is not -infinity)
+  uint64_t mx0 = ballot(A[0] != NEG), mx1 = ballot(A[1] != NEG);
+  uint64_t my0 = ballot(B[0] != NEG), my1 = ballot(B[1] != NEG);
+  if ((mx0 | mx1 | my0 | my1) == 0) return R_CONT;
   const int d0 = e.d;
   const int d_end = smin(d_last, d0 + (1 << 20));  // 32-bit sums exact
   const int gap = P.gap, X = smin(P.X, 1 << 29);  // see fast_interior
   const int m = e.m, n = e.n;
-  const int lane = lane_id();
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
-  // bare codes: cell j of lane l is x = base + C*l + j and takes a[x - 1]
+  // bare codes: cell j of lane l is x = base + 2l + j and takes a[x - 1]
   // and b[d - x - 1]
   int fa[C], fb[C];
   auto load_fa = [&]() {
@@ -906,17 +906,19 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   uint32_t acc = 0;         // live-span cells of the antidiagonals done
   int tbest = 0, bd = -1, bxa = 0;
   int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
+  int rem = 0;              // edge blocks: d_end - d
+  // masks of the block's antidiagonals in lanes (lane k + 2: the block's
+  // k-th; lanes 0 and 1: the two before it), per register j and word
+  int ml0 = 0, mh0 = 0, ml1 = 0, mh1 = 0;
 
-  // antidiagonal d from prev (d-1) and pp (d-2); pp receives d.  Returns 1
-  // when the top cell turned finite, after two dead antidiagonals, or (edge
-  // blocks) past the last antidiagonal of the range; 0 to go on.
-  auto body = [&](auto edge_tag, int (&prev)[C], int (&pp)[C], int in) -> int {
+  // antidiagonal d + k from prev (d+k-1, masks mp0/mp1) and pp (d+k-2,
+  // masks mpp0/mpp1); pp and its masks receive d + k.  True (odd k only)
+  // after two dead antidiagonals or when the band reached lane 62, or (edge
+  // blocks) at the last antidiagonal of the range.
+  auto body = [&](auto edge_tag, int (&prev)[C], int (&pp)[C],
+                  const uint64_t& mp0, const uint64_t& mp1, uint64_t& mpp0,
+                  uint64_t& mpp1, int in, int k) -> bool {
     constexpr bool EDGE = decltype(edge_tag)::value;
-    if constexpr (EDGE)
-      acc += (uint32_t)smax(smin(smax(U1, U2) + 1, mrel) -
-                            smax(smin(L1, L2 + 1), pm) + 1, 0);
-    else
-      acc += (uint32_t)(smax(U1, U2) - smin(L1, L2 + 1) + 2);
     const int thr = tv - X;
     int v[C];
 #pragma unroll
@@ -932,52 +934,60 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       else sim = tab[fa[j] + fb[j]];
       v[j] = max(max(up, prev[j]), dg + sim);
     }
-    int L0 = 64 * C, U0 = -1, lm = NEG;
+    uint64_t f[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) {
-      bool f = v[j] >= thr;
-      if constexpr (EDGE) {  // y > n below pm, x > m above mrel
-        const int pos = lane * C + j;
-        f = f && pos >= pm && pos <= mrel;
-      }
-      pp[j] = f ? v[j] : NEG;
-      lm = max(lm, pp[j]);
-      const uint64_t fm = ballot(f);
-      L0 = smin(L0, ((int)__builtin_ctzg(fm, 64) << LOG2C) + j);
-      U0 = smax(U0, ((63 - (int)__builtin_clzg(fm, 64)) << LOG2C) + j);
+      f[j] = ballot(v[j] >= thr);
+      if constexpr (EDGE)  // y > n below pm, x > m above mrel
+        f[j] &= ballot((uint32_t)(lane * C + j - (pm + k)) <=
+                       (uint32_t)(mrel - (pm + k)));
     }
+    int vn[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      vn[j] = __builtin_amdgcn_inverse_ballot_w64(f[j]) ? v[j] : NEG;
+    // away from the edges a cell with v > tv >= thr is finite
+    const int lm = EDGE ? max(vn[0], vn[1]) : max(v[0], v[1]);
     const uint64_t imp = ballot(lm > tv);
-    if (imp) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) pp[j] = vn[j];
+    if (__builtin_expect(imp != 0, 0)) {
       int l0 = __builtin_ctzll(imp);
       int wm = __builtin_amdgcn_readlane(lm, l0);
       if (imp & (imp - 1)) {
         wm = uni(wave_max(lm));
         l0 = __builtin_ctzll(ballot(lm == wm));
       }
-      int jf = C - 1;
-#pragma unroll
-      for (int j = C - 1; j >= 0; --j)
-        if (pp[j] == wm) jf = j;
+      // lowest x of the lane: cell 0 if it holds the maximum
+      const int jf = __builtin_amdgcn_readlane(pp[0] == wm ? 0 : 1, l0);
       tv = wm;
       tbest = wm;  // T, bx, by are formed on hand-over
-      bd = d;
-      bxa = base + (l0 << LOG2C) + __builtin_amdgcn_readlane(jf, l0);
+      bd = d + k;
+      bxa = base + (l0 << 1) + jf;
     }
-    L2 = L1; U2 = U1;
-    L1 = L0; U1 = U0;
+    mpp0 = f[0];
+    mpp1 = f[1];
+    ml0 = xd_writelane_i32((int)(uint32_t)f[0], k + 2, ml0);
+    mh0 = xd_writelane_i32((int)(uint32_t)(f[0] >> 32), k + 2, mh0);
+    ml1 = xd_writelane_i32((int)(uint32_t)f[1], k + 2, ml1);
+    mh1 = xd_writelane_i32((int)(uint32_t)(f[1] >> 32), k + 2, mh1);
     tv -= gap;
-    ++d;
-    if constexpr (EDGE) ++pm;
     // the target codes move one cell up; lane 0 takes `in`
     const int top = fb[C - 1];
 #pragma unroll
     for (int j = C - 1; j > 0; --j) fb[j] = fb[j - 1];
     fb[0] = __builtin_amdgcn_update_dpp(in, top, 0x138, 0xf, 0xf, false);
-    if ((uint32_t)smax(U1, U2) >= (uint32_t)TOP) return 1;
-    if constexpr (EDGE) {
-      if (d > d_end) return 1;
+    if (k & 1) {
+      const uint64_t o = mp0 | mp1 | f[0] | f[1];
+      if (o == 0) return true;
+      uint32_t hw = (uint32_t)(o >> 32);  // lanes 62, 63 (see fast_interior)
+      opaque_s(hw);
+      if (hw >= (1u << 30)) return true;
     }
-    return 0;
+    if constexpr (EDGE) {
+      if (k >= rem) return true;  // d + k is d_end
+    }
+    return false;
   };
   // blocks of QB antidiagonals; the codes entering lane 0 during a block
   // are read from the ring at its start (blocks of 8 for byte codes keep the
@@ -986,11 +996,36 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   int x[C], y[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) { x[j] = A[j]; y[j] = B[j]; }
-  bool newest_in_y = false;
-  int st = 0;
   while (d <= d_end) {
+    {
+      const uint64_t o = mx0 | mx1 | my0 | my1;
+      if ((uint32_t)(o >> 32) >= (1u << 30)) {
+        // the band reached lane 62: slide the window up by the whole lanes
+        // below the lowest finite cell of d-1 and d-2
+        const int sl = __builtin_ctzll(o);
+        if (sl < 2) break;
+        const int src = lane + sl;
+        const bool in = src < 64;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x[j]);
+          const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y[j]);
+          // target codes move with their cells; stray codes at the top
+          // lanes are not used before they have moved out (see
+          // fast_interior)
+          fb[j] = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb[j]);
+          x[j] = in ? pn : NEG;
+          y[j] = in ? po : NEG;
+        }
+        mx0 >>= sl; mx1 >>= sl; my0 >>= sl; my1 >>= sl;
+        base += sl << 1;
+        cover_a<ALPHA>(e, w, S, base + 2 * 64 - 2);
+        load_fa();
+      }
+    }
     pm = d - n - base;
     mrel = m - base;
+    rem = d_end - d;
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + QB - 1);
     uint32_t qw[ALPHA == 0 ? 1 : 2];
@@ -1002,6 +1037,16 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
 #pragma unroll
     for (int i = 0; i < (ALPHA == 0 ? 1 : 2); ++i)
       qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+    ml0 = xd_writelane_i32((int)(uint32_t)my0, 0, ml0);
+    mh0 = xd_writelane_i32((int)(uint32_t)(my0 >> 32), 0, mh0);
+    ml1 = xd_writelane_i32((int)(uint32_t)my1, 0, ml1);
+    mh1 = xd_writelane_i32((int)(uint32_t)(my1 >> 32), 0, mh1);
+    ml0 = xd_writelane_i32((int)(uint32_t)mx0, 1, ml0);
+    mh0 = xd_writelane_i32((int)(uint32_t)(mx0 >> 32), 1, mh0);
+    ml1 = xd_writelane_i32((int)(uint32_t)mx1, 1, ml1);
+    mh1 = xd_writelane_i32((int)(uint32_t)(mx1 >> 32), 1, mh1);
+    int nk = QB;  // antidiagonals computed by the block
+    bool newest_in_y = false;
     auto run_block = [&](auto edge_tag) {
 #pragma unroll
       for (int k = 0; k < QB; k += 2) {
@@ -1011,48 +1056,68 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
         const int in1 = ALPHA == 0
             ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
             : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
-        st = body(edge_tag, x, y, in0);
-        if (st) { newest_in_y = true; return; }
-        st = body(edge_tag, y, x, in1);
-        if (st) { newest_in_y = false; return; }
+        if (body(edge_tag, x, y, mx0, mx1, my0, my1, in0, k)) {
+          nk = k + 1; newest_in_y = true; return;
+        }
+        if (body(edge_tag, y, x, my0, my1, mx0, mx1, in1, k + 1)) {
+          nk = k + 2; return;
+        }
       }
     };
-    if (pm + QB - 1 <= 0 && mrel >= TOP && d + QB - 1 <= d_end)
+    if (pm + QB - 1 <= 0 && mrel >= 2 * 64 - 1 && rem >= QB - 1)
       run_block(std::false_type{});
     else
       run_block(std::true_type{});
-    if (st == 0) continue;  // QB antidiagonals done; x holds the newest
-    if (U1 != TOP) break;   // two dead antidiagonals, or the end of the range
-    // the top cell turned finite: slide the window up by the whole lanes
-    // below the lowest finite cell of d and d-1
-    const int sl = smin(L1, L2) >> LOG2C;
-    if (sl < 1) break;
-    const int src = lane + sl;
-    const bool in = src < 64;
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int nw = newest_in_y ? y[j] : x[j];
-      const int od = newest_in_y ? x[j] : y[j];
-      const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, nw);
-      const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, od);
-      // target codes move with their cells; stray codes at the top lanes
-      // are not used before they have moved out (see fast_interior)
-      fb[j] = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb[j]);
-      x[j] = in ? pn : NEG;
-      y[j] = in ? po : NEG;
+    {
+      // live-span cells of the block's antidiagonals (see fast_interior):
+      // lane k + 2 forms antidiagonal k's span from the finite ranges of the
+      // antidiagonals in lanes k + 1 (a) and k (b)
+      auto range = [&](uint32_t l0, uint32_t h0, uint32_t l1, uint32_t h1,
+                       int& L, int& U) {
+        const uint32_t c0 = min((uint32_t)__builtin_ctzg(l0, -1),
+                                (uint32_t)__builtin_ctzg(h0, -1) | 32u);
+        const uint32_t c1 = min((uint32_t)__builtin_ctzg(l1, -1),
+                                (uint32_t)__builtin_ctzg(h1, -1) | 32u);
+        const uint32_t z0 = min((uint32_t)__builtin_clzg(h0, -1),
+                                (uint32_t)__builtin_clzg(l0, -1) | 32u);
+        const uint32_t z1 = min((uint32_t)__builtin_clzg(h1, -1),
+                                (uint32_t)__builtin_clzg(l1, -1) | 32u);
+        // (an empty mask gives c = z = 2^32 - 1: L above, U below any cell)
+        L = (int)min(min(c0, 64u) * 2, min(c1, 64u) * 2 + 1);
+        U = max(c0 >= 64u ? -1 : (int)(63 - z0) * 2,
+                c1 >= 64u ? -1 : (int)(63 - z1) * 2 + 1);
+      };
+      int La, Ua, Lb, Ub;
+      range((uint32_t)wave_shr1(ml0, 0), (uint32_t)wave_shr1(mh0, 0),
+            (uint32_t)wave_shr1(ml1, 0), (uint32_t)wave_shr1(mh1, 0), La, Ua);
+      range((uint32_t)wave_shr1(wave_shr1(ml0, 0), 0),
+            (uint32_t)wave_shr1(wave_shr1(mh0, 0), 0),
+            (uint32_t)wave_shr1(wave_shr1(ml1, 0), 0),
+            (uint32_t)wave_shr1(wave_shr1(mh1, 0), 0), Lb, Ub);
+      const int kk = lane - 2;
+      const int lo = max(min(La, Lb + 1), pm + kk);
+      const int hi = min(max(Ua, Ub) + 1, mrel);
+      const bool live = Ua >= 0 || Ub >= 0;
+      const int cnt = (kk >= 0 && kk < nk && live) ? max(hi - lo + 1, 0) : 0;
+      acc += (uint32_t)sum_lanes_0_31(cnt);
     }
-    newest_in_y = false;
-    st = 0;
-    L1 -= sl << LOG2C; U1 -= sl << LOG2C;
-    L2 -= sl << LOG2C; U2 -= sl << LOG2C;
-    base += sl << LOG2C;
-    cover_a<ALPHA>(e, w, S, base + TOP - 1);
-    load_fa();
+    d += nk;
+    if (newest_in_y) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int t = x[j];
+        x[j] = y[j];
+        y[j] = t;
+      }
+    }
+    mx0 = ballot(x[0] != NEG); mx1 = ballot(x[1] != NEG);
+    my0 = ballot(y[0] != NEG); my1 = ballot(y[1] != NEG);
+    if ((mx0 | mx1 | my0 | my1) == 0) break;  // two dead antidiagonals
   }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
-    A[j] = newest_in_y ? y[j] : x[j];
-    B[j] = newest_in_y ? x[j] : y[j];
+    A[j] = x[j];
+    B[j] = y[j];
   }
   e.base = base;
   e.d = d;
@@ -1062,10 +1127,19 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     e.bx = bxa;
     e.by = bd - bxa;
   }
-  e.L1 = U1 < 0 ? DEAD_L : base + L1;
-  e.U1 = U1 < 0 ? DEAD_U : base + U1;
-  e.L2 = U2 < 0 ? DEAD_L : base + L2;
-  e.U2 = U2 < 0 ? DEAD_U : base + U2;
+  auto lo_of = [&](uint64_t m0, uint64_t m1) {
+    return smin(m0 ? 2 * __builtin_ctzll(m0) : DEAD_L,
+                m1 ? 2 * __builtin_ctzll(m1) + 1 : DEAD_L);
+  };
+  auto hi_of = [&](uint64_t m0, uint64_t m1) {
+    return smax(m0 ? 2 * (63 - __builtin_clzll(m0)) : DEAD_U,
+                m1 ? 2 * (63 - __builtin_clzll(m1)) + 1 : DEAD_U);
+  };
+  const bool lx = (mx0 | mx1) != 0, ly = (my0 | my1) != 0;
+  e.L1 = lx ? base + lo_of(mx0, mx1) : DEAD_L;
+  e.U1 = lx ? base + hi_of(mx0, mx1) : DEAD_U;
+  e.L2 = ly ? base + lo_of(my0, my1) : DEAD_L;
+  e.U2 = ly ? base + hi_of(my0, my1) : DEAD_U;
   int r = R_CONT;
   const int mv = window_move<ALPHA, C>(e, A, B, sy, w, S, e.L1, e.L2, e.U1,
                                        e.U2);
