@@ -1858,16 +1858,38 @@ __global__ void xd_mark_kernel(const int32_t* seeds, int32_t n_seeds,
 __global__ void xd_validate_kernel(const uint8_t* seqs, const int64_t* offsets,
                                    int32_t n_seqs, int32_t asize,
                                    uint8_t* state) {
+  // four sequences per wave, 16 lanes each, 32-bit words (the stream is
+  // read in whole words, as the extension kernels read it); the state and
+  // offsets of a sequence are loaded together
   const int lane = lane_id();
+  const int g = lane >> 4, gl = lane & 15;
   const int wpb = blockDim.x >> 6;
-  for (int64_t s = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); s < n_seqs;
-       s += (int64_t)gridDim.x * wpb) {
-    if (state[s] == 0) continue;  // uniform per wave
-    const int64_t a = offsets[s], b = offsets[s + 1];
+  const int64_t wave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  const uint32_t* words = (const uint32_t*)seqs;
+  for (int64_t s0 = wave * 4; s0 < n_seqs; s0 += nwaves * 4) {
+    const int64_t s = s0 + g;
     int found = 0;
-    for (int64_t i = a + lane; i < b; i += 64) found |= seqs[i] >= asize;
+    if (s < n_seqs) {
+      const int st = state[s];
+      const int64_t a = offsets[s], b = offsets[s + 1];
+      if (st == 1 && b > a) {
+        const int64_t wend = (b - 1) >> 2;
+#pragma unroll 4
+        for (int64_t wi = (a >> 2) + gl; wi <= wend; wi += 16) {
+          const uint32_t v = words[wi];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t p = wi * 4 + i;
+            found |= (p >= a && p < b &&
+                      ((v >> (8 * i)) & 0xFFu) >= (uint32_t)asize);
+          }
+        }
+      }
+    }
     const uint64_t any = ballot(found != 0);
-    if (lane == 0 && any) state[s] = 2;
+    if (gl == 0 && s < n_seqs && ((any >> (16 * g)) & 0xFFFFull))
+      state[s] = 2;
   }
 }
 
@@ -1973,6 +1995,7 @@ __global__ void xd_combine_kernel(Params P, void* out_v) {
     const int64_t oq = P.offsets[q], ot = P.offsets[t];
     const Src S = make_src(P);
     int seed = 0;
+#pragma unroll 4
     for (int u = 0; u < k; ++u) {
       const int ca = sym_at(P, S, oq + qp + u), cb = sym_at(P, S, ot + tp + u);
       if (P.alphabet == 0) seed += (ca == cb ? P.mat_s : P.mis_s) + 2 * P.gap;

@@ -294,3 +294,38 @@ def test_graph_after_workspace_growth():
         assert not compare(r.run(small, scheme, graph=True, dev=dev_s), ref_s)
     finally:
         r.ctx.close()
+
+
+def test_symbol_check_word_boundaries():
+    """Out-of-alphabet codes are found wherever they sit in a sequence
+    (first, last or inner byte; sequences of 1..130 bytes that share 32-bit
+    words with their neighbours), and a bad code in a neighbour never marks
+    a sequence: statuses equal the oracle's seed by seed."""
+    from paper_2304_08662_amd import xdrop
+    r = Runner()
+    try:
+        rng = np.random.default_rng(34)
+        pairs = []
+        for i in range(400):
+            lq = int(rng.integers(1, 131))
+            q = rng.integers(0, 20, lq).astype(np.uint8)
+            t = q.copy()
+            kind = i % 5
+            if kind == 1:
+                q[0] = 20 + int(rng.integers(0, 12))     # first byte
+            elif kind == 2:
+                t[-1] = 20 + int(rng.integers(0, 12))    # last byte
+            elif kind == 3:
+                q[int(rng.integers(0, lq))] = 31         # anywhere
+            k = int(rng.integers(0, min(lq, 6) + 1))
+            pos = int(rng.integers(0, lq - k + 1))
+            pairs.append((q, t, pos, pos, k))
+        batch = make_batch(pairs, 20)
+        scheme = inputs.Scheme(20, gap=-2, X=10,
+                               matrix=inputs.stand_in_substitution_matrix())
+        ref = oracle_run(batch, scheme)
+        g = r.run(batch, scheme)
+        assert not compare(g, ref)
+        assert (g["status"] == xdrop.E_SYMBOL).sum() == 240
+    finally:
+        r.ctx.close()
