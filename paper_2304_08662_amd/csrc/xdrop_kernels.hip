@@ -676,11 +676,15 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     const int vi = EDGE ? vn : v;
     const uint64_t imp = ballot(vi > tv);
     pp = vn;
-    if (__builtin_expect(imp != 0, 0)) {
+    // (DNA: T improves on a large share of the antidiagonals of related
+    // pairs, so the update is laid out inline; byte codes keep it apart)
+    if (ALPHA == 0 ? imp != 0 : __builtin_expect(imp != 0, 0)) {
       // usually a single lane beats T: its value is the new best
       int l0 = __builtin_ctzll(imp);
       int wm = __builtin_amdgcn_readlane(vi, l0);
-      if (imp & (imp - 1)) {
+      uint32_t nimp = (uint32_t)__builtin_popcountll(imp);
+      opaque_s(nimp);  // (one s_bcnt1, not a 64-bit x & (x - 1))
+      if (nimp > 1) {
         wm = uni(wave_max(vi));
         l0 = __builtin_ctzll(ballot(vi == wm));
       }
@@ -954,7 +958,9 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     if (__builtin_expect(imp != 0, 0)) {
       int l0 = __builtin_ctzll(imp);
       int wm = __builtin_amdgcn_readlane(lm, l0);
-      if (imp & (imp - 1)) {
+      uint32_t nimp = (uint32_t)__builtin_popcountll(imp);
+      opaque_s(nimp);
+      if (nimp > 1) {
         wm = uni(wave_max(lm));
         l0 = __builtin_ctzll(ballot(lm == wm));
       }
