@@ -644,12 +644,12 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
 
   // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
   // finite-lane masks mp and mpp; pp and mpp receive d + k (the two
-  // antidiagonals and their masks swap roles every step).  True (odd k only)
-  // after two dead antidiagonals or when the band reached lane 62, or (edge
-  // blocks) at the last antidiagonal of the range; the reason is read from
-  // the masks and d after the block.  (Two dead antidiagonals at an even k
-  // are followed by one more, dead as well, that adds no live-span cell.)
-  // d itself moves once per block.
+  // antidiagonals and their masks swap roles every step).  True (odd k)
+  // when the band reached lane 62, (k = 3 mod 4) after two dead
+  // antidiagonals, or (edge blocks) at the last antidiagonal of the range;
+  // the reason is read from the masks and d after the block.  (Two dead
+  // antidiagonals may be followed by up to three more, dead as well, that
+  // add no live-span cell.)  d itself moves once per block.
   auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
                   uint64_t& mpp, int k) -> bool {
     constexpr bool EDGE = decltype(edge_tag)::value;
@@ -704,7 +704,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     }
     if (k & 1) {
       const uint64_t o = mp | fm;
-      if (o == 0) return true;
+      if ((k & 3) == 3 && o == 0) return true;
       // lane 62 or 63 finite; tested on the high word, since a 64-bit
       // compare would run on the vector unit
       uint32_t hw = (uint32_t)(o >> 32);
