@@ -96,8 +96,11 @@ typedef struct {
 
 /* Launch options (host struct; NULL = defaults). */
 enum {
-    XDROP_VARIANT_AUTO = 0,      /* choose per batch (tuned table, else WAVE;
-                                    PAIR runs as WAVE when a band cap is set) */
+    XDROP_VARIANT_AUTO = 0,      /* choose per batch: the tuned table, else
+                                    PLAIN when the whole batch fits in one
+                                    wave of the persistent grid (every
+                                    extension starts at once), else WAVE;
+                                    PAIR runs as WAVE when a band cap is set */
     XDROP_VARIANT_WAVE = 1,      /* one wavefront per extension */
     XDROP_VARIANT_WORKGROUP = 2, /* one 4-wave workgroup per extension */
     XDROP_VARIANT_PLAIN = 3,     /* one wave per extension, one launch wave per

@@ -168,7 +168,7 @@ xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
     r.order = o->order;
     if (o->waves_per_cu) r.waves_per_cu = o->waves_per_cu;
   }
-  if (!r.variant) r.variant = XDROP_VARIANT_WAVE;
+  // (AUTO stays 0 here: enqueue picks PLAIN or WAVE from the batch size)
   // the pair kernel keeps no per-antidiagonal band width: a band cap runs on
   // the wave kernel
   if (r.variant == XDROP_VARIANT_PAIR && r.band_cap > 0)
@@ -251,6 +251,16 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   P.chunk = o.chunk;
   P.band_cap = o.band_cap;
   P.gen_slots = c->gen_slots;
+  if (o.variant == XDROP_VARIANT_AUTO) {
+    // a batch within one wave of the persistent grid starts every extension
+    // at once: the plain form (one launched wave per extension) then does
+    // the same work without the queue and the longest-first order, which
+    // it measured faster on such batches; larger batches take the queue
+    const int a0 = P.alphabet;
+    const int64_t waves = (int64_t)c->num_cu * c->blocks_per_cu[a0] * WPB;
+    o.variant = (o.waves_per_cu == 0 && (int64_t)n_items <= waves)
+                    ? XDROP_VARIANT_PLAIN : XDROP_VARIANT_WAVE;
+  }
   const bool plain = o.variant == XDROP_VARIANT_PLAIN;
   P.flags = plain ? F_PLAIN : 0;
 
