@@ -189,9 +189,9 @@ def main():
                          "times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the work shards by seeds with no exchange; see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU "
+              "path (the work would shard by seeds, with no exchange "
+              "between GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
