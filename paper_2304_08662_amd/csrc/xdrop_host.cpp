@@ -182,10 +182,13 @@ void drop_graphs(xdrop_ctx* c);
 
 // Device buffers of the launch sequence.  Graphs captured earlier hold the
 // old workspace address, so a move drops them.
-int ensure_workspace(xdrop_ctx* c, size_t bytes) {
+int ensure_workspace(xdrop_ctx* c, size_t bytes, hipStream_t st) {
   if (!c->counters) {
+    // zeroed once here (a kernel on the batch's stream, never inside a
+    // capture: graphs are recorded after this call); from then on the last
+    // kernel of every batch leaves them zero for the next one
     HIP_OK(hipMalloc(&c->counters, C_COUNT * sizeof(int32_t)));
-    HIP_OK(hipMemset(c->counters, 0, C_COUNT * sizeof(int32_t)));
+    HIP_OK(launch_reset(c->counters, st));
   }
   if (!c->gen_scratch) {
     HIP_OK(hipMalloc(&c->gen_scratch,
@@ -221,7 +224,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   xdrop_options o = resolve(c, sc, opts);
   const int32_t n_items = 2 * n_seeds;
   Layout L = layout(n_items, n_seqs);
-  rc = ensure_workspace(c, L.total);
+  rc = ensure_workspace(c, L.total, st);
   if (rc != XDROP_OK) return rc;
   char* ws = (char*)c->ws;
 
@@ -275,7 +278,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   }
   const bool timed = ev != nullptr;
   if (timed) HIP_OK(hipEventRecord(ev[0], st));
-  HIP_OK(launch_reset(c->counters, st));
+  // (the counters were left zero by the previous batch's combine kernel)
   if (P.alphabet == 1) {
     P.seq_bad = (const uint8_t*)(ws + L.bad);
     HIP_OK(launch_validate(d_seqs, d_offsets, n_seqs, P.seeds, n_seeds,
@@ -442,7 +445,7 @@ int xdrop_last_stats(xdrop_ctx* c, int64_t* counts, int32_t n_counts) {
       return fail(c, hipErrorUnknown);
   }
   for (int i = 0; i < n_counts; ++i)
-    counts[i] = i < 6 ? h[C_TIER0 + i] : 0;
+    counts[i] = i < 6 ? h[C_REPORT + i] : 0;
   return XDROP_OK;
 }
 
@@ -513,7 +516,7 @@ extern "C" int xdrop_extend_batch_graph(
   }
   // everything that allocates or queries happens before the capture
   Layout L = layout(2 * n_seeds, n_seqs);
-  rc = ensure_workspace(c, L.total);  // (drops the graphs if it moves)
+  rc = ensure_workspace(c, L.total, st);  // (drops the graphs if it moves)
   if (rc != XDROP_OK) return rc;
   for (int a = 0; a < 2; ++a)
     if (!c->blocks_per_cu[a]) c->blocks_per_cu[a] = wave_blocks_per_cu(a);

@@ -85,7 +85,8 @@ enum {
   C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8, pair, general
   C_HIST = 16,      // longest-first ordering: bucket sizes
   C_CURSOR = C_HIST + 256,  // bucket write cursors
-  C_COUNT = C_CURSOR + 256
+  C_REPORT = C_CURSOR + 256,  // the finished batch's tier counts (6)
+  C_COUNT = C_REPORT + 8
 };
 constexpr int NBUCKET = 256;
 

@@ -1981,7 +1981,17 @@ __global__ void xd_scatter_kernel(const int32_t* seeds, const int64_t* offsets,
 }
 
 // Seed level: score = left + seed score + right and positions (Sec. 4.1.1).
+// It is the last kernel of every batch: block 0 also moves the tier counts to
+// the report slots and zeroes the other counters for the next batch (no
+// kernel of this batch uses them any more), which saves a reset launch.
 __global__ void xd_combine_kernel(Params P, void* out_v) {
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < C_REPORT; i += blockDim.x) {
+      if (i >= C_TIER0 && i < C_TIER0 + 6)
+        P.counters[C_REPORT + (i - C_TIER0)] = P.counters[i];
+      P.counters[i] = 0;
+    }
+  }
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= P.n_seeds) return;
   struct Out {
