@@ -2011,7 +2011,9 @@ __global__ void xd_combine_kernel(Params P, void* out_v) {
     const int64_t oq = P.offsets[q], ot = P.offsets[t];
     const Src S = make_src(P);
     int seed = 0;
-#pragma unroll 4
+    // (independent loads: unrolled so that a seed's symbols are in flight
+    // together)
+#pragma unroll 16
     for (int u = 0; u < k; ++u) {
       const int ca = sym_at(P, S, oq + qp + u), cb = sym_at(P, S, ot + tp + u);
       if (P.alphabet == 0) seed += (ca == cb ? P.mat_s : P.mis_s) + 2 * P.gap;
