@@ -557,6 +557,9 @@ __device__ __forceinline__ int step(Ext& e, int (&A)[C], int (&B)[C],
 // scalar (s) or vector (v) register.
 __device__ __forceinline__ void opaque_s(uint32_t& v) { asm("" : "+s"(v)); }
 __device__ __forceinline__ void opaque_v(int& v) { asm("" : "+v"(v)); }
+// The same as a volatile statement: the instructions that form v stay ahead
+// of the branches that follow (the compiler may not sink them past one).
+__device__ __forceinline__ void pin_v(int& v) { asm volatile("" : "+v"(v)); }
 
 // A value that the compiler keeps in a VGPR (a loop-invariant operand of a
 // per-lane select, which may not read two SGPRs).
@@ -675,7 +678,11 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     // improvement test need not wait for the select
     const int vi = EDGE ? vn : v;
     const uint64_t imp = ballot(vi > tv);
-    pp = vn;
+    // (the select before the improvement branch: the next antidiagonal's
+    // neighbour moves then need not wait for it after the branch)
+    int vk = vn;
+    pin_v(vk);
+    pp = vk;
     // (DNA: T improves on a large share of the antidiagonals of related
     // pairs, so the update is laid out inline; byte codes keep it apart)
     if (ALPHA == 0 ? imp != 0 : __builtin_expect(imp != 0, 0)) {
