@@ -18,14 +18,18 @@
 //  * pruning, the running best T (wave max reduction only on antidiagonals
 //    where some lane beats T, detected with a ballot) and the finite range
 //    (L, U) come from per-register ballots;
-//  * the window slides up by one lane (C cells) when the band reaches its top
-//    and the bottom lane is dead; when the band is wider than the window the
-//    tile widens in place (C -> 2C, registers redistributed with
-//    ds_bpermute) up to C = 8 (512 cells); wider bands go to a workgroup
+//  * the window slides up by whole lanes when the band reaches its top, by as
+//    many as the dead lanes below the band allow; when the band is wider than
+//    the window the tile widens in place (C -> 2C, registers redistributed
+//    with ds_bpermute) up to C = 8 (512 cells); wider bands go to a workgroup
 //    tier with rings in device memory;
+//  * for C = 1 and 2, blocks of antidiagonals run in unrolled interior loops
+//    on the finite-lane masks, with the live-span count formed per block on
+//    the vector unit (fast_interior, fast_interior_multi);
 //  * sequences stream through per-wave LDS rings (2-bit DNA or byte codes),
 //    read backwards for left extensions (the paper's op() transform);
-//  * extensions are pulled from a device queue by persistent waves.
+//  * extensions are pulled from a device queue by persistent waves, or for a
+//    batch that starts at once, one launched wave per extension.
 // All arithmetic is int32 integer VALU/SALU; no MFMA.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -574,7 +578,9 @@ __device__ __forceinline__ int in_vgpr(int v) {
 //   hi_d = min(64 - clz(M1 | M2), m - base),
 // where the clamps matter only near the matrix edges; blocks of 16
 // antidiagonals that stay clear of both edges skip them and the per-lane
-// edge masks.  The two top lanes stay -infinity at the start of every pair
+// edge masks.  The live-span count sum(hi_d - lo_d + 1) is formed once per
+// block on the vector unit from the masks, which the block keeps in lanes
+// of two registers.  The two top lanes stay -infinity at the start of every pair
 // of antidiagonals (the band grows by at most one lane per antidiagonal, so
 // the top lane is still -infinity one antidiagonal later): the neighbour
 // exchange is then a wave rotation that brings -infinity to lane 0, and the
@@ -636,7 +642,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
   uint32_t acc = 0;         // sum over d of (65 - live-span cells)
   int tbest = 0, bd = -1, bxa = 0;  // last new best: V value, d, x
-  int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
+  int pm = 0, mrel = 0;     // d - n - base, m - base (edge clamps and masks)
   int rem = 0;              // edge blocks: d_end - d
   uint32_t mw = 0;          // DNA: match word of the block
   // finite-lane masks of the block's antidiagonals for the live-span count,
@@ -1844,8 +1850,8 @@ __global__ __launch_bounds__(GEN_THREADS) void xd_general_kernel(Params P) {
 }
 
 // ------------------------------------------------------------------ misc
-// Zero the counters (a kernel rather than a memset so that the launch
-// sequence can be captured in a graph).
+// Zero the counters once, when they are allocated (a kernel on the batch's
+// stream); every batch's combine kernel leaves them zero for the next one.
 __global__ void xd_reset_kernel(int32_t* counters) {
   for (int i = threadIdx.x; i < C_COUNT; i += blockDim.x) counters[i] = 0;
 }
