@@ -1877,7 +1877,7 @@ __global__ void xd_mark_kernel(const int32_t* seeds, int32_t n_seeds,
 __global__ void xd_validate_kernel(const uint8_t* seqs, const int64_t* offsets,
                                    int32_t n_seqs, int32_t asize,
                                    uint8_t* state) {
-  // four sequences per wave, 16 lanes each, 32-bit words (the stream is
+  // four sequences per wave, 16 lanes each, 8-byte loads (the stream is
   // read in whole words, as the extension kernels read it); the state and
   // offsets of a sequence are loaded together
   const int lane = lane_id();
@@ -1886,6 +1886,11 @@ __global__ void xd_validate_kernel(const uint8_t* seqs, const int64_t* offsets,
   const int64_t wave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * wpb;
   const uint32_t* words = (const uint32_t*)seqs;
+  const uint2* pairs = (const uint2*)seqs;
+  // 8-byte pairs of words whose second word still holds stream bytes (the
+  // stream is read in whole words only)
+  const int64_t tw = (offsets[n_seqs] + 3) >> 2;
+  const bool al8 = ((uintptr_t)seqs & 7) == 0;
   for (int64_t s0 = wave * 4; s0 < n_seqs; s0 += nwaves * 4) {
     const int64_t s = s0 + g;
     int found = 0;
@@ -1893,15 +1898,24 @@ __global__ void xd_validate_kernel(const uint8_t* seqs, const int64_t* offsets,
       const int st = state[s];
       const int64_t a = offsets[s], b = offsets[s + 1];
       if (st == 1 && b > a) {
-        const int64_t wend = (b - 1) >> 2;
-#pragma unroll 4
-        for (int64_t wi = (a >> 2) + gl; wi <= wend; wi += 16) {
-          const uint32_t v = words[wi];
+        const int64_t pend = (b - 1) >> 3;
+#pragma unroll 2
+        for (int64_t pi = (a >> 3) + gl; pi <= pend; pi += 16) {
+          uint32_t v[2];
+          if (al8 && 2 * pi + 1 < tw) {
+            const uint2 q = pairs[pi];
+            v[0] = q.x;
+            v[1] = q.y;
+          } else {
+            v[0] = words[2 * pi];
+            // (2 pi + 1 past the stream: none of its bytes is checked)
+            v[1] = 2 * pi + 1 < tw ? words[2 * pi + 1] : 0;
+          }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int64_t p = wi * 4 + i;
+          for (int i = 0; i < 8; ++i) {
+            const int64_t p = pi * 8 + i;
             found |= (p >= a && p < b &&
-                      ((v >> (8 * i)) & 0xFFu) >= (uint32_t)asize);
+                      ((v[i >> 2] >> (8 * (i & 3))) & 0xFFu) >= (uint32_t)asize);
           }
         }
       }
@@ -1973,7 +1987,7 @@ __global__ void xd_scan_kernel(int32_t* counters) {
 
 // Items of one block claim their slots bucket by bucket: one device atomic
 // per (block, bucket) instead of one per item.
-__global__ void xd_scatter_kernel(const int32_t* seeds, const int64_t* offsets,
+__global__ __launch_bounds__(1024) void xd_scatter_kernel(const int32_t* seeds, const int64_t* offsets,
                                   int32_t n_seqs, int32_t n_items,
                                   int32_t* counters, int32_t* order) {
   __shared__ int h[NBUCKET];
@@ -2089,8 +2103,10 @@ hipError_t launch_order(const int32_t* seeds, const int64_t* offsets,
   hipLaunchKernelGGL(xd_hist_kernel, dim3(std::max(grid, 1)), dim3(256), 0, s,
                      seeds, offsets, n_seqs, n_items, counters);
   hipLaunchKernelGGL(xd_scan_kernel, dim3(1), dim3(NBUCKET), 0, s, counters);
-  hipLaunchKernelGGL(xd_scatter_kernel, dim3((n_items + 255) / 256), dim3(256),
-                     0, s, seeds, offsets, n_seqs, n_items, counters, order);
+  // (blocks of 1024 items: a quarter of the contended cursor atomics)
+  hipLaunchKernelGGL(xd_scatter_kernel, dim3((n_items + 1023) / 1024),
+                     dim3(1024), 0, s, seeds, offsets, n_seqs, n_items,
+                     counters, order);
   return hipGetLastError();
 }
 
