@@ -44,6 +44,15 @@ namespace xd {
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Hide a value's origin from the optimiser (no instruction is emitted), so
+// that it cannot turn the operations that follow into longer forms: a
+// scalar (s) or vector (v) register.
+__device__ __forceinline__ void opaque_s(uint32_t& v) { asm("" : "+s"(v)); }
+__device__ __forceinline__ void opaque_v(int& v) { asm("" : "+v"(v)); }
+// The same as a volatile statement: the instructions that form v stay ahead
+// of the branches that follow (the compiler may not sink them past one).
+__device__ __forceinline__ void pin_v(int& v) { asm volatile("" : "+v"(v)); }
+
 // Lane l receives lane l-1's value; lane 0 receives `fill`.
 __device__ __forceinline__ int wave_shr1(int v, int fill) {
   return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);
@@ -53,17 +62,24 @@ __device__ __forceinline__ int wave_shl1(int v, int fill) {
   return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
 }
 
-// Maximum over the wave, returned as a uniform value.
+// Maximum over the wave, returned as a uniform value.  (Each permutation
+// gives every lane a source, so bound_ctrl changes nothing; it lets the
+// compiler fold each move into its max.)
 __device__ __forceinline__ int wave_max(int v) {
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, true));
   int r0 = __builtin_amdgcn_readlane(v, 0);
   int r1 = __builtin_amdgcn_readlane(v, 16);
   int r2 = __builtin_amdgcn_readlane(v, 32);
   int r3 = __builtin_amdgcn_readlane(v, 48);
-  return max(max(r0, r1), max(r2, r3));
+  // (the row maxima are combined on the scalar unit, not moved back into
+  // vector registers for a three-input max)
+  uint32_t a = (uint32_t)max(r0, r1), b = (uint32_t)max(r2, r3);
+  opaque_s(a);
+  opaque_s(b);
+  return max((int)a, (int)b);
 }
 
 // v_writelane_b32: lane `lane` of `old` takes the uniform value `val`.  This
@@ -556,14 +572,6 @@ __device__ __forceinline__ int step(Ext& e, int (&A)[C], int (&B)[C],
 }
 
 // ------------------------------------------------------------------ interior
-// Hide a value's origin from the optimiser (no instruction is emitted), so
-// that it cannot turn the operations that follow into longer forms: a
-// scalar (s) or vector (v) register.
-__device__ __forceinline__ void opaque_s(uint32_t& v) { asm("" : "+s"(v)); }
-__device__ __forceinline__ void opaque_v(int& v) { asm("" : "+v"(v)); }
-// The same as a volatile statement: the instructions that form v stay ahead
-// of the branches that follow (the compiler may not sink them past one).
-__device__ __forceinline__ void pin_v(int& v) { asm volatile("" : "+v"(v)); }
 
 // A value that the compiler keeps in a VGPR (a loop-invariant operand of a
 // per-lane select, which may not read two SGPRs).
@@ -668,14 +676,19 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       int t = __builtin_amdgcn_sbfe((int)mw, 2 * k, 1);  // -1: match
       opaque_v(t);  // keeps the bit select one v_bfi (not compare + select)
       sim = (t & vmat) | (~t & vmis);
+      opaque_v(sim);  // (the select stays whole, so the add below is VOP2)
     } else {
       sim = tab[(int)fa + fb];
     }
     // (every lane of a wave rotation has a source, so bound_ctrl changes
-    // nothing; it lets the compiler fold the move into its user)
+    // nothing; it lets the compiler fold the move into its user, a VOP2
+    // add and max here: the inner max is kept apart from the outer, which
+    // would otherwise make a three-input max that takes no DPP operand)
     const int up = __builtin_amdgcn_update_dpp(0, prev, 0x13C, 0xf, 0xf, true);
     const int dg = __builtin_amdgcn_update_dpp(0, pp, 0x13C, 0xf, 0xf, true);
-    const int v = max(max(up, prev), dg + sim);
+    int uh = max(up, prev);
+    opaque_v(uh);
+    const int v = max(uh, dg + sim);
     uint64_t fm = ballot(v >= thr);
     if constexpr (EDGE)  // y > n below pm, x > m above mrel
       fm &= ballot((uint32_t)(lane - (pm + k)) <= (uint32_t)(mrel - (pm + k)));
