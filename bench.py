@@ -35,15 +35,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_tokens(text: str) -> str:
+    """C++ source with its comments dropped and every run of white space made
+    one blank: what the compiler sees, so that an edit of comments or layout
+    leaves it unchanged.  Comment marks inside string and character
+    literals are left alone."""
+    import re
+    pat = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/',
+                     re.S)
+    out = pat.sub(lambda m: m.group(0) if m.group(0)[0] in "\"'" else " ",
+                  text)
+    return " ".join(out.split())
+
+
 def kernel_source_digest() -> str:
-    """sha256 of the kernel sources: HBM byte counters stored under profiles/
-    apply only to the kernel build they were taken on."""
+    """sha256 of the kernel sources' code (comments and layout left out): HBM
+    byte counters stored under profiles/ apply only to the kernel code they
+    were taken on."""
     import hashlib
     h = hashlib.sha256()
     for rel in ("paper_2304_08662_amd/csrc/xdrop_kernels.hip",
                 "paper_2304_08662_amd/csrc/xdrop_internal.h"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(code_tokens(f.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()
 
 

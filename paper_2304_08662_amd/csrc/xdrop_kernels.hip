@@ -88,13 +88,26 @@ __device__ __forceinline__ int wave_max(int v) {
 extern "C" __device__ int xd_writelane_i32(int val, int lane, int old) __asm(
     "llvm.amdgcn.writelane.i32");
 
-// Sum of lanes 0..31 (a uniform value).
-__device__ __forceinline__ int sum_lanes_0_31(int v) {
+// Sums of the lanes of each row of 16, in every lane of the row.
+__device__ __forceinline__ int row_sums(int v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
   v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
   v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
   v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+  return v;
+}
+
+// Sum of lanes 0..31 (a uniform value).
+__device__ __forceinline__ int sum_lanes_0_31(int v) {
+  v = row_sums(v);
   return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16);
+}
+
+// Sum of all 64 lanes (a uniform value).
+__device__ __forceinline__ int sum_lanes(int v) {
+  v = row_sums(v);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) {
@@ -584,9 +597,9 @@ __device__ __forceinline__ int in_vgpr(int v) {
 // scalar ranges (positions relative to the window base):
 //   lo_d = max(ctz(M1 | M2 << 1), d - n - base),
 //   hi_d = min(64 - clz(M1 | M2), m - base),
-// where the clamps matter only near the matrix edges; blocks of 16
-// antidiagonals that stay clear of both edges skip them and the per-lane
-// edge masks.  The live-span count sum(hi_d - lo_d + 1) is formed once per
+// where the clamps matter only near the matrix edges; blocks (32
+// antidiagonals for DNA, 16 for byte codes) that stay clear of both edges
+// skip them and the per-lane edge masks.  The live-span count sum(hi_d - lo_d + 1) is formed once per
 // block on the vector unit from the masks, which the block keeps in lanes
 // of two registers.  The two top lanes stay -infinity at the start of every pair
 // of antidiagonals (the band grows by at most one lane per antidiagonal, so
@@ -652,7 +665,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int tbest = 0, bd = -1, bxa = 0;  // last new best: V value, d, x
   int pm = 0, mrel = 0;     // d - n - base, m - base (edge clamps and masks)
   int rem = 0;              // edge blocks: d_end - d
-  uint32_t mw = 0;          // DNA: match word of the block
+  // antidiagonals per block: DNA reads two match words (the block's fixed
+  // work then spreads over 32 steps); bytes keep 16 target codes in qw
+  constexpr int KB = ALPHA == 0 ? 32 : 16;
+  uint32_t mw[2] = {0, 0};  // DNA: match words of the block (k < 16, >= 16)
   // finite-lane masks of the block's antidiagonals for the live-span count,
   // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
   // the two antidiagonals before the block, lane k + 2 the block's k-th
@@ -673,7 +689,8 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     const int thr = tv - X;
     int sim;
     if constexpr (ALPHA == 0) {
-      int t = __builtin_amdgcn_sbfe((int)mw, 2 * k, 1);  // -1: match
+      // -1: match
+      int t = __builtin_amdgcn_sbfe((int)mw[k >> 4], 2 * (k & 15), 1);
       opaque_v(t);  // keeps the bit select one v_bfi (not compare + select)
       sim = (t & vmat) | (~t & vmis);
       opaque_v(sim);  // (the select stays whole, so the add below is VOP2)
@@ -775,11 +792,14 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     mrel = m - base;
     rem = d_end - d;
     const int e0 = d - base;
-    cover_b<ALPHA>(e, w, S, e0 + 15);
+    cover_b<ALPHA>(e, w, S, e0 + KB - 1);
     if constexpr (ALPHA == 0) {
-      // codes of b[e0 - lane - 1 + k], k < 16, against the lane's query code
-      const uint32_t xw = Ring<0>::read(w.rb, e0 - lane - 1) ^ fa;
-      mw = ~(xw | (xw >> 1)) & 0x55555555u;
+      // codes of b[e0 - lane - 1 + k], k < 32, against the lane's query code
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t xw = Ring<0>::read(w.rb, e0 - lane - 1 + 16 * h) ^ fa;
+        mw[h] = ~(xw | (xw >> 1)) & 0x55555555u;
+      }
     } else {
       Ring<1>::read<4>(w.rb, e0, qw);
 #pragma unroll
@@ -789,18 +809,18 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     mh = xd_writelane_i32((int)(uint32_t)(m2 >> 32), 0, mh);
     ml = xd_writelane_i32((int)(uint32_t)m1, 1, ml);
     mh = xd_writelane_i32((int)(uint32_t)(m1 >> 32), 1, mh);
-    int nk = 16;  // antidiagonals computed by the block
+    int nk = KB;  // antidiagonals computed by the block
     bool newest_in_y = false;
     auto run_block = [&](auto edge_tag) {
 #pragma unroll
-      for (int k = 0; k < 16; k += 2) {
+      for (int k = 0; k < KB; k += 2) {
         if (body(edge_tag, x, y, m1, m2, k)) {
           nk = k + 1; newest_in_y = true; return;
         }
         if (body(edge_tag, y, x, m2, m1, k + 1)) { nk = k + 2; return; }
       }
     };
-    if (pm + 15 <= 0 && mrel >= 63 && rem >= 15)
+    if (pm + KB - 1 <= 0 && mrel >= 63 && rem >= KB - 1)
       run_block(std::false_type{});
     else
       run_block(std::true_type{});
@@ -825,7 +845,8 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       const bool live = (al | ah | bl | bh) != 0;
       const int cnt = (kk >= 0 && kk < nk)
                           ? (live ? 65 - max(hi - lo + 1, 0) : 65) : 0;
-      acc += (uint32_t)sum_lanes_0_31(cnt);
+      // (lanes 2 .. KB + 1 hold counts)
+      acc += (uint32_t)(KB + 2 <= 32 ? sum_lanes_0_31(cnt) : sum_lanes(cnt));
     }
     d += nk;
     if (newest_in_y) {
