@@ -601,13 +601,13 @@ __device__ __forceinline__ int in_vgpr(int v) {
 // antidiagonals for DNA, 16 for byte codes) that stay clear of both edges
 // skip them and the per-lane edge masks.  The live-span count sum(hi_d - lo_d + 1) is formed once per
 // block on the vector unit from the masks, which the block keeps in lanes
-// of two registers.  The two top lanes stay -infinity at the start of every pair
-// of antidiagonals (the band grows by at most one lane per antidiagonal, so
-// the top lane is still -infinity one antidiagonal later): the neighbour
-// exchange is then a wave rotation that brings -infinity to lane 0, and the
-// band is tested against the top only every second antidiagonal.  When the
-// band reaches lane 62 the window slides up in place by the dead lanes below
-// the band.  DNA scores come from a per-block match word (bit 2k of lane l:
+// of two registers.  The top G lanes (four for DNA, two for byte codes)
+// stay -infinity at the start of every group of G antidiagonals (the band
+// grows by at most one lane per antidiagonal, so the top lane is still
+// -infinity G - 1 antidiagonals later): the neighbour exchange is then a
+// wave rotation that brings -infinity to lane 0, and the band is tested
+// against the top only every G-th antidiagonal.  When the band reaches lane
+// 64 - G the window slides up in place by the dead lanes below the band.  DNA scores come from a per-block match word (bit 2k of lane l:
 // the codes of cell base + l agree on antidiagonal d + k); byte codes move
 // one cell up per antidiagonal, lane 0 taking the next queued code, and
 // index the score table.  The loop computes antidiagonals up to m + n - 1
@@ -668,6 +668,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // antidiagonals per block: DNA reads two match words (the block's fixed
   // work then spreads over 32 steps); bytes keep 16 target codes in qw
   constexpr int KB = ALPHA == 0 ? 32 : 16;
+  // top lanes kept -infinity between the tests against the top: DNA tests
+  // with the dead test, every fourth antidiagonal
+  constexpr int G = ALPHA == 0 ? 4 : 2;
   uint32_t mw[2] = {0, 0};  // DNA: match words of the block (k < 16, >= 16)
   // finite-lane masks of the block's antidiagonals for the live-span count,
   // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
@@ -677,8 +680,8 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
 
   // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
   // finite-lane masks mp and mpp; pp and mpp receive d + k (the two
-  // antidiagonals and their masks swap roles every step).  True (odd k)
-  // when the band reached lane 62, (k = 3 mod 4) after two dead
+  // antidiagonals and their masks swap roles every step).  True (k = G - 1
+  // mod G) when the band reached lane 64 - G, (k = 3 mod 4) after two dead
   // antidiagonals, or (edge blocks) at the last antidiagonal of the range;
   // the reason is read from the masks and d after the block.  (Two dead
   // antidiagonals may be followed by up to three more, dead as well, that
@@ -745,14 +748,14 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       const int in = (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
       fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
     }
-    if (k & 1) {
+    if ((k & (G - 1)) == G - 1) {
       const uint64_t o = mp | fm;
       if ((k & 3) == 3 && o == 0) return true;
-      // lane 62 or 63 finite; tested on the high word, since a 64-bit
-      // compare would run on the vector unit
+      // one of the top G lanes finite; tested on the high word, since a
+      // 64-bit compare would run on the vector unit
       uint32_t hw = (uint32_t)(o >> 32);
       opaque_s(hw);
-      if (hw >= (1u << 30)) return true;
+      if (hw >= (1u << (32 - G))) return true;
     }
     if constexpr (EDGE) {
       if (k >= rem) return true;  // d + k is d_end
@@ -763,11 +766,12 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // x (mask m1) holds d-1 and y (mask m2) holds d-2 at the start of a block
   int x = A[0], y = B[0];
   while (d <= d_end) {
-    if (cz < 2) {
-      // the band reached lane 62: slide the window up by the lanes below
-      // the lowest finite cell of d-1 and d-2 (they are -infinity on both)
+    if (cz < G) {
+      // the band reached lane 64 - G: slide the window up by the lanes
+      // below the lowest finite cell of d-1 and d-2 (they are -infinity on
+      // both)
       const int sl = __builtin_ctzll(m1 | m2);
-      if (cz + sl < 2) break;
+      if (cz + sl < G) break;
       const int src = lane + sl;
       const bool in = src < 64;
       const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
