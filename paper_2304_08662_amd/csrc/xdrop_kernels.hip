@@ -662,7 +662,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
   uint32_t acc = 0;         // sum over d of (65 - live-span cells)
-  int tbest = 0, bd = -1, bxa = 0;  // last new best: V value, d, x
+  // last new best: its antidiagonal, its x, and its lane (folded into x
+  // once per block: base moves only between blocks); T itself follows from
+  // tv, which is T in the frame of the next antidiagonal
+  int bd = -1, bxa = 0, bln = 0;
   int pm = 0, mrel = 0;     // d - n - base, m - base (edge clamps and masks)
   int rem = 0;              // edge blocks: d_end - d
   // antidiagonals per block: DNA reads two match words (the block's fixed
@@ -734,10 +737,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
         wm = uni(wave_max(vi));
         l0 = __builtin_ctzll(ballot(vi == wm));
       }
-      tv = wm;
-      tbest = wm;  // T, bx, by are formed on hand-over
+      tv = wm;  // T, bx, by are formed on hand-over
       bd = d + k;
-      bxa = base + l0;
+      bln = l0;
     }
     mpp = fm;
     ml = xd_writelane_i32((int)(uint32_t)fm, k + 2, ml);
@@ -852,6 +854,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       // (lanes 2 .. KB + 1 hold counts)
       acc += (uint32_t)(KB + 2 <= 32 ? sum_lanes_0_31(cnt) : sum_lanes(cnt));
     }
+    if (bd >= d) bxa = base + bln;  // a new best in this block
     d += nk;
     if (newest_in_y) {
       const int t = x;
@@ -872,8 +875,8 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   e.base = base;
   e.d = d;
   e.W += (int64_t)65 * (d - d0) - (int64_t)acc;
+  e.T = tv + gap * d;
   if (bd >= 0) {
-    e.T = tbest + gap * bd;
     e.bx = bxa;
     e.by = bd - bxa;
   }
