@@ -599,21 +599,22 @@ __device__ __forceinline__ int in_vgpr(int v) {
 //   hi_d = min(64 - clz(M1 | M2), m - base),
 // where the clamps matter only near the matrix edges; blocks (32
 // antidiagonals for DNA, 16 for byte codes) that stay clear of both edges
-// skip them and the per-lane edge masks.  The live-span count sum(hi_d - lo_d + 1) is formed once per
-// block on the vector unit from the masks, which the block keeps in lanes
-// of two registers.  The top G lanes (four for DNA, two for byte codes)
-// stay -infinity at the start of every group of G antidiagonals (the band
-// grows by at most one lane per antidiagonal, so the top lane is still
+// skip them and the per-lane edge masks.  The live-span count
+// sum(hi_d - lo_d + 1) is formed once per block on the vector unit from the
+// masks, which the block keeps in lanes of two registers.  The top G = 4
+// lanes stay -infinity at the start of every group of G antidiagonals (the
+// band grows by at most one lane per antidiagonal, so the top lane is still
 // -infinity G - 1 antidiagonals later): the neighbour exchange is then a
 // wave rotation that brings -infinity to lane 0, and the band is tested
 // against the top only every G-th antidiagonal.  When the band reaches lane
-// 64 - G the window slides up in place by the dead lanes below the band.  DNA scores come from a per-block match word (bit 2k of lane l:
-// the codes of cell base + l agree on antidiagonal d + k); byte codes move
-// one cell up per antidiagonal, lane 0 taking the next queued code, and
-// index the score table.  The loop computes antidiagonals up to m + n - 1
-// and hands over to the generic step (state as that step expects) at the
-// last one, after two dead antidiagonals, or when the band fills the window;
-// R_ESC when the window can neither slide nor stay.
+// 64 - G the window slides up in place by the dead lanes below the band.
+// DNA scores come from per-block match words (bit 2k of lane l: the codes
+// of cell base + l agree on antidiagonal d + k); byte codes move one cell up
+// per antidiagonal, lane 0 taking the next queued code, and index the score
+// table.  The loop computes antidiagonals up to m + n - 1 and hands over to
+// the generic step (state as that step expects) at the last one, after two
+// dead antidiagonals, or when the band fills the window; R_ESC when the
+// window can neither slide nor stay.
 template <int ALPHA>
 __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
                                              Syms<ALPHA, 1>& sy,
@@ -671,9 +672,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // antidiagonals per block: DNA reads two match words (the block's fixed
   // work then spreads over 32 steps); bytes keep 16 target codes in qw
   constexpr int KB = ALPHA == 0 ? 32 : 16;
-  // top lanes kept -infinity between the tests against the top: DNA tests
+  // top lanes kept -infinity between the tests against the top, which run
   // with the dead test, every fourth antidiagonal
-  constexpr int G = ALPHA == 0 ? 4 : 2;
+  constexpr int G = 4;
   uint32_t mw[2] = {0, 0};  // DNA: match words of the block (k < 16, >= 16)
   // finite-lane masks of the block's antidiagonals for the live-span count,
   // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
