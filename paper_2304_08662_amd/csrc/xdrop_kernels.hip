@@ -212,7 +212,7 @@ template <>
 struct Ring<1> {  // one byte per code
   static constexpr int RS = 2048;
   static constexpr int RW = RS / 4;
-  static constexpr int MIRROR = 5;
+  static constexpr int MIRROR = 9;         // reads of up to 8 words
   static constexpr int WORDS = RW + MIRROR;
   static constexpr int CH = 512;           // 8 per lane
 
@@ -597,9 +597,9 @@ __device__ __forceinline__ int in_vgpr(int v) {
 // scalar ranges (positions relative to the window base):
 //   lo_d = max(ctz(M1 | M2 << 1), d - n - base),
 //   hi_d = min(64 - clz(M1 | M2), m - base),
-// where the clamps matter only near the matrix edges; blocks (32
-// antidiagonals for DNA, 16 for byte codes) that stay clear of both edges
-// skip them and the per-lane edge masks.  The live-span count
+// where the clamps matter only near the matrix edges; blocks of 32
+// antidiagonals that stay clear of both edges skip them and the per-lane
+// edge masks.  The live-span count
 // sum(hi_d - lo_d + 1) is formed once per block on the vector unit from the
 // masks, which the block keeps in lanes of two registers.  The top G = 4
 // lanes stay -infinity at the start of every group of G antidiagonals (the
@@ -669,9 +669,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int bd = -1, bxa = 0, bln = 0;
   int pm = 0, mrel = 0;     // d - n - base, m - base (edge clamps and masks)
   int rem = 0;              // edge blocks: d_end - d
-  // antidiagonals per block: DNA reads two match words (the block's fixed
-  // work then spreads over 32 steps); bytes keep 16 target codes in qw
-  constexpr int KB = ALPHA == 0 ? 32 : 16;
+  // antidiagonals per block (the block's fixed work spreads over 32
+  // steps): DNA reads two match words, bytes 32 target codes into qw
+  constexpr int KB = 32;
   // top lanes kept -infinity between the tests against the top, which run
   // with the dead test, every fourth antidiagonal
   constexpr int G = 4;
@@ -680,7 +680,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
   // the two antidiagonals before the block, lane k + 2 the block's k-th
   int ml = 0, mh = 0;
-  uint32_t qw[4] = {0, 0, 0, 0};  // bytes: codes entering lane 0
+  uint32_t qw[8] = {};  // bytes: codes entering lane 0
 
   // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
   // finite-lane masks mp and mpp; pp and mpp receive d + k (the two
@@ -808,9 +808,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
         mw[h] = ~(xw | (xw >> 1)) & 0x55555555u;
       }
     } else {
-      Ring<1>::read<4>(w.rb, e0, qw);
+      Ring<1>::read<8>(w.rb, e0, qw);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+      for (int i = 0; i < 8; ++i) qw[i] = (uint32_t)in_vgpr((int)qw[i]);
     }
     ml = xd_writelane_i32((int)(uint32_t)m2, 0, ml);
     mh = xd_writelane_i32((int)(uint32_t)(m2 >> 32), 0, mh);
