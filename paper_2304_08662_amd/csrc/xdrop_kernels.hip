@@ -1051,9 +1051,9 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     return false;
   };
   // blocks of QB antidiagonals; the codes entering lane 0 during a block
-  // are read from the ring at its start (blocks of 8 for byte codes keep the
-  // register footprint small)
-  constexpr int QB = ALPHA == 0 ? 16 : 8;
+  // are read from the ring at its start (one word of DNA codes, four words
+  // of byte codes)
+  constexpr int QB = 16;
   int x[C], y[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) { x[j] = A[j]; y[j] = B[j]; }
@@ -1089,14 +1089,14 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     rem = d_end - d;
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + QB - 1);
-    uint32_t qw[ALPHA == 0 ? 1 : 2];
+    uint32_t qw[ALPHA == 0 ? 1 : 4];
     if constexpr (ALPHA == 0) {
       qw[0] = Ring<0>::read(w.rb, e0);
     } else {
-      Ring<1>::read<2>(w.rb, e0, qw);
+      Ring<1>::read<4>(w.rb, e0, qw);
     }
 #pragma unroll
-    for (int i = 0; i < (ALPHA == 0 ? 1 : 2); ++i)
+    for (int i = 0; i < (ALPHA == 0 ? 1 : 4); ++i)
       qw[i] = (uint32_t)in_vgpr((int)qw[i]);
     ml0 = xd_writelane_i32((int)(uint32_t)my0, 0, ml0);
     mh0 = xd_writelane_i32((int)(uint32_t)(my0 >> 32), 0, mh0);
