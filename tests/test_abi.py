@@ -71,3 +71,6 @@ def test_product_package_does_not_import_the_oracle():
                 assert "import oracle" not in text, f
                 assert "xdrop_oracle" not in text, f
                 assert "liboracle" not in text, f
+                # nor the CPU emulation of the kernels (tests/emu)
+                assert "xdrop_emu" not in text, f
+                assert "tests/emu" not in text, f

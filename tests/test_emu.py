@@ -1,0 +1,146 @@
+"""The library's kernels and host code built for the CPU (tests/emu: every GPU
+thread a fiber, the lanes of a wave meeting at every cross-lane operation)
+against the oracle, bit-exact.  These run the exact sources of libxdrop.so
+without a GPU: long extensions whose sequences wrap the LDS rings, the
+register tiers up to 512 cells, the workgroup tier, every launch form, and
+samples of the dna-100k workload.  A lane that diverges at a cross-lane
+operation, or a wave that stops making progress, aborts the run."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2304_08662_amd import inputs, xdrop
+from tests.xdrop_testutil import compare, make_batch, oracle_run, product_scoring
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DNA = {c: i for i, c in enumerate("ACGT")}
+
+
+@pytest.fixture(scope="module")
+def emu():
+    from tests.xdrop_emu import EmuLib, build
+    build()
+    e = EmuLib()
+    yield e
+    e.close()
+
+
+def _enc(s):
+    return np.array([DNA[c] for c in s], dtype=np.uint8)
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+def test_golden(emu):
+    for name, a, b, X, best, x, y, W in _rows("extensions.txt"):
+        batch = make_batch([(_enc(a), _enc(b), 0, 0, 0)], 4)
+        g = emu.run(batch, product_scoring(inputs.Scheme(4, 1, -1, -1, int(X))))[0]
+        assert (g["score"], g["q_end"], g["t_end"]) == (int(best), int(x), int(y)), name
+        if W != "-":
+            assert g["cells"] == 1 + int(W), name
+    for row in _rows("seeds.txt"):
+        name, q, t, qp, tp, k, X = row[:7]
+        batch = make_batch([(_enc(q), _enc(t), int(qp), int(tp), int(k))], 4)
+        g = emu.run(batch, product_scoring(inputs.Scheme(4, 1, -1, -1, int(X))))[0]
+        got = [int(g[f]) for f in ("score", "left", "seed_score", "right",
+                                   "q_begin", "q_end", "t_begin", "t_end")]
+        assert got == list(map(int, row[7:])), name
+
+
+def _fuzz(rng, n, alphabet, lmax, related_p=0.6):
+    from tests.test_gpu_parity import _fuzz_pairs
+    return _fuzz_pairs(rng, n, alphabet, lmax, related_p)
+
+
+@pytest.mark.parametrize("X", [0, 3, 50, 2**31 - 1])
+def test_fuzz_dna(emu, X):
+    rng = np.random.default_rng([40, X % 1000])
+    batch = make_batch(_fuzz(rng, 60, 4, 300 if X > 1000 else 600), 4)
+    scheme = inputs.Scheme(4, 2, -3, -2, X)
+    assert not compare(emu.run(batch, product_scoring(scheme)),
+                       oracle_run(batch, scheme))
+
+
+@pytest.mark.parametrize("X", [0, 49, 2**31 - 1])
+def test_fuzz_protein(emu, X):
+    rng = np.random.default_rng([41, X % 1000])
+    batch = make_batch(_fuzz(rng, 60, 20, 250 if X > 1000 else 500), 20)
+    scheme = inputs.Scheme(20, gap=-2, X=X,
+                           matrix=inputs.stand_in_substitution_matrix())
+    assert not compare(emu.run(batch, product_scoring(scheme)),
+                       oracle_run(batch, scheme))
+
+
+def test_long_byte_codes_wrap_rings(emu):
+    """Byte-coded pairs of 3,000-10,000 codes: every extension passes the
+    2,048-code LDS ring several times (the mirror words and the ring margin
+    of the 4- and 8-cell tiers included); related and unrelated pairs, left
+    and right extensions, seeds near both ends, and an X large enough that
+    windows widen to 8 cells per lane and beyond."""
+    rng = np.random.default_rng(42)
+    M = inputs.stand_in_substitution_matrix()
+    pairs = []
+    for i in range(8):
+        L = int(rng.integers(3000, 10001))
+        q = rng.integers(0, 20, L).astype(np.uint8)
+        if i % 2 == 0:
+            t, _ = inputs.mutate(rng, q, 0.2, 0.03, 0.03, 20)
+        else:
+            t = rng.integers(0, 20, int(rng.integers(3000, 10001))).astype(np.uint8)
+        k = 6
+        where = [0.02, 0.5, 0.98][i % 3]
+        qp = int(where * (len(q) - k))
+        tp = min(int(where * (len(t) - k)), len(t) - k)
+        t = t.copy()
+        t[tp:tp + k] = q[qp:qp + k]
+        pairs.append((q, t, qp, tp, k))
+    batch = make_batch(pairs, 20)
+    for X in (49, 400):
+        scheme = inputs.Scheme(20, gap=-2, X=X, matrix=M)
+        g = emu.run(batch, product_scoring(scheme))
+        assert not compare(g, oracle_run(batch, scheme)), X
+    stats = emu.last_stats()
+    assert stats[2] + stats[3] + stats[5] > 0, stats  # wide tiers reached
+
+
+def test_wide_bands_all_tiers(emu):
+    rng = np.random.default_rng(43)
+    pairs = []
+    for L in (40, 300, 600, 1100):
+        q = rng.integers(0, 4, L).astype(np.uint8)
+        t = rng.integers(0, 4, L + int(rng.integers(-20, 20))).astype(np.uint8)
+        pairs.append((q, t, 0, 0, 0))
+    batch = make_batch(pairs, 4)
+    scheme = inputs.Scheme(4, 1, -1, -1, 2**31 - 1)
+    assert not compare(emu.run(batch, product_scoring(scheme)),
+                       oracle_run(batch, scheme))
+    stats = emu.last_stats()
+    assert stats[3] >= 1 and stats[5] >= 1, stats
+
+
+def test_launch_forms(emu):
+    rng = np.random.default_rng(44)
+    batch = make_batch(_fuzz(rng, 40, 4, 900, related_p=0.4), 4)
+    scheme = inputs.Scheme(4, 1, -1, -1, 40)
+    ref = oracle_run(batch, scheme)
+    for v, tile, chunk, order in [(1, 1, 1, 0), (1, 4, 8, 1), (3, 2, 1, 0),
+                                  (2, 1, 1, 0), (4, 1, 1, 0), (4, 2, 4, 1)]:
+        g = emu.run(batch, product_scoring(scheme),
+                    xdrop.options(v, tile, chunk, 0, order))
+        assert not compare(g, ref), (v, tile, chunk, order)
+
+
+def test_dna_100k_sample(emu):
+    """Seeds of the dna-100k workload (X = 50): the widest bands of its
+    0.4% sample (up to ~700 cells, past the 512-cell register window) and
+    ordinary related and unrelated pairs of 1-30 kb."""
+    batch, scheme = inputs.workload("dna-100k", 0.004)
+    idx = [166, 76, 107, 330, 0, 1, 2, 3, 4, 5]
+    b = batch.subset(idx)
+    g = emu.run(b, product_scoring(scheme))
+    assert not compare(g, oracle_run(b, scheme))
+    assert emu.last_stats()[5] >= 2  # bands past 512 cells
