@@ -53,7 +53,7 @@ typedef enum {
     XDROP_E_BUDGET = -5,   /* serving: request can never fit the budget */
     XDROP_E_SYMBOL = -6,   /* per seed: a code >= alphabet_size */
     XDROP_BAND_OVERFLOW = -7, /* per seed: band wider than opts->band_cap,
-                                 or than 65536 cells (workgroup tier) */
+                                 or than 65536 cells (device-memory tier) */
     XDROP_PENDING = 1      /* serving: request not finished yet */
 } xdrop_status;
 
@@ -102,7 +102,9 @@ enum {
                                     extension starts at once), else WAVE;
                                     PAIR runs as WAVE when a band cap is set */
     XDROP_VARIANT_WAVE = 1,      /* one wavefront per extension */
-    XDROP_VARIANT_WORKGROUP = 2, /* one 4-wave workgroup per extension */
+    XDROP_VARIANT_WORKGROUP = 2, /* one 4-wave workgroup per extension
+                                    (window of 1,024..2,048 cells over the
+                                    registers of the four waves) */
     XDROP_VARIANT_PLAIN = 3,     /* one wave per extension, one launch wave per
                                     extension, no queue: the baseline form */
     XDROP_VARIANT_PAIR = 4       /* two extensions per wavefront (32-cell
@@ -196,7 +198,8 @@ int xdrop_last_timing(xdrop_ctx *ctx, float *ms, int32_t n,
 /* Statistics of the last batch on this context (after stream sync):
  * counts of extensions finished at each tile width: counts[0..3] = 1, 2, 4,
  * 8 cells per lane (wave kernel), counts[4] = pair kernel, counts[5] =
- * workgroup tier. */
+ * workgroup (block) tier, bands of 513..2,048 cells, counts[6] =
+ * device-memory tier, wider bands. */
 int xdrop_last_stats(xdrop_ctx *ctx, int64_t *counts, int32_t n_counts);
 
 /* ---------------------------------------------------------------- serving

@@ -43,6 +43,7 @@ struct xdrop_ctx {
   int32_t* gen_scratch = nullptr;
   int gen_slots = 32;
   int pair_blocks_per_cu[2] = {0, 0};
+  int block_blocks_per_cu[2] = {0, 0};
   int blocks_per_cu[2] = {0, 0};  // [alphabet]
   bool have_tuned[2] = {false, false};
   xdrop_options tuned[2];
@@ -61,7 +62,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-  size_t items, order, gen_q, esc_q, bad, total;
+  size_t items, order, gen_q, dev_q, esc_q, bad, total;
 };
 
 Layout layout(int32_t n_items, int32_t n_seqs) {
@@ -76,6 +77,7 @@ Layout layout(int32_t n_items, int32_t n_seqs) {
   L.items = take(ni * sizeof(ItemResult));
   L.order = take(ni * 4);
   L.gen_q = take(ni * 4);
+  L.dev_q = take(ni * 4);
   L.esc_q = take(ni * 4);
   L.bad = take((size_t)std::max(n_seqs, 1));
   L.total = off;
@@ -234,6 +236,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   P.items = (ItemResult*)(ws + L.items);
   P.counters = c->counters;
   P.gen_queue = (int32_t*)(ws + L.gen_q);
+  P.dev_queue = (int32_t*)(ws + L.dev_q);
   P.esc_queue = (int32_t*)(ws + L.esc_q);
   P.gen_scratch = c->gen_scratch;
   P.n_seqs = n_seqs;
@@ -331,6 +334,12 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     if (timed) HIP_OK(hipEventRecord(ev[2], st));
     if (timed) HIP_OK(hipEventRecord(ev[3], st));
   }
+  // extensions whose band outgrew one wave's window: the block tier, and
+  // beyond 2,048 cells the device-memory tier (both leave at once when
+  // nothing was handed to them)
+  if (!c->block_blocks_per_cu[a]) c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
+  HIP_OK(launch_block(P, std::min(c->num_cu * c->block_blocks_per_cu[a],
+                                  n_items), st));
   HIP_OK(launch_general(P, c->gen_slots, st));
   if (timed) HIP_OK(hipEventRecord(ev[4], st));
   HIP_OK(launch_combine(P, d_results, st));
@@ -445,7 +454,7 @@ int xdrop_last_stats(xdrop_ctx* c, int64_t* counts, int32_t n_counts) {
       return fail(c, hipErrorUnknown);
   }
   for (int i = 0; i < n_counts; ++i)
-    counts[i] = i < 6 ? h[C_REPORT + i] : 0;
+    counts[i] = i < N_TIERS ? h[C_REPORT + i] : 0;
   return XDROP_OK;
 }
 
@@ -518,8 +527,13 @@ extern "C" int xdrop_extend_batch_graph(
   Layout L = layout(2 * n_seeds, n_seqs);
   rc = ensure_workspace(c, L.total, st);  // (drops the graphs if it moves)
   if (rc != XDROP_OK) return rc;
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a) {
     if (!c->blocks_per_cu[a]) c->blocks_per_cu[a] = wave_blocks_per_cu(a);
+    if (!c->block_blocks_per_cu[a])
+      c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
+    if (!c->pair_blocks_per_cu[a])
+      c->pair_blocks_per_cu[a] = pair_blocks_per_cu(a);
+  }
   GraphEntry g;
   g.seqs = d_seqs; g.offsets = d_offsets; g.seeds = d_seeds;
   g.results = d_results; g.n_seqs = n_seqs; g.n_seeds = n_seeds;

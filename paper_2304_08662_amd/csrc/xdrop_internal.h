@@ -22,8 +22,8 @@ constexpr int32_t DEAD_U = -(1 << 30);
 constexpr int WAVE = 64;
 constexpr int WPB = 4;                // waves per block of the wave kernels
 constexpr int TABLE_DIM = 32;         // substitution table is 32 x 32
-constexpr int GEN_THREADS = 256;      // general (workgroup) tier block size
-constexpr int GEN_CAP = 1 << 16;      // general tier band capacity (cells)
+constexpr int GEN_THREADS = 256;      // device-memory tier block size
+constexpr int GEN_CAP = 1 << 16;      // device-memory tier band capacity
 
 // Per-extension result written by the extension kernels.
 struct ItemResult {
@@ -55,9 +55,10 @@ struct Params {
   const int32_t* order;      // processing order (F_ORDERED) or null
   int32_t* counters;         // queue heads and tier statistics
   const uint8_t* seq_bad;    // per-sequence check (BYTE): 2 = bad symbol
-  int32_t* gen_queue;        // items handed to the general tier
+  int32_t* gen_queue;        // items handed to the block tier
+  int32_t* dev_queue;        // items handed to the device-memory tier
   int32_t* esc_queue;        // items handed on by the pair kernel
-  int32_t* gen_scratch;      // general tier rings
+  int32_t* gen_scratch;      // device-memory tier rings
   int32_t n_seqs;
   int32_t n_seeds;
   int32_t n_items;
@@ -70,25 +71,29 @@ struct Params {
   int32_t X;                 // clamped to X_CLAMP
   int32_t mat_s, mis_s;      // DNA: match - 2 gap, mismatch - 2 gap
   int32_t max_abs;           // max |entry| + 2 |gap|  (value bound per d)
-  int32_t gen_slots;         // concurrent general-tier workgroups
+  int32_t gen_slots;         // concurrent device-memory tier workgroups
   int16_t table[TABLE_DIM * TABLE_DIM];  // BYTE: sim - 2 gap, row = query
 };
 
 // Counter layout (int32 slots).
 enum {
   C_HEAD = 0,       // main queue head
-  C_GEN_TAIL = 1,   // general queue tail
-  C_GEN_HEAD = 2,   // general queue head
+  C_GEN_TAIL = 1,   // block tier queue tail
+  C_GEN_HEAD = 2,   // block tier queue head
   C_ESC_TAIL = 3,   // pair kernel hand-on queue tail
   C_ESC_HEAD = 4,   // its head (wave kernel)
   C_PAIR_HEAD = 5,  // pair kernel queue head
-  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8, pair, general
+  C_DEV_TAIL = 6,   // device-memory tier queue tail
+  C_DEV_HEAD = 7,   // its head
+  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8 cells per lane,
+                    // pair, block, device memory
   C_HIST = 16,      // longest-first ordering: bucket sizes
   C_CURSOR = C_HIST + 256,  // bucket write cursors
-  C_REPORT = C_CURSOR + 256,  // the finished batch's tier counts (6)
+  C_REPORT = C_CURSOR + 256,  // the finished batch's tier counts (7)
   C_COUNT = C_REPORT + 8
 };
 constexpr int NBUCKET = 256;
+constexpr int N_TIERS = 7;
 
 }  // namespace xd
 
@@ -110,6 +115,8 @@ hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
 hipError_t launch_wave(const Params& P, int grid, hipStream_t s);
 hipError_t launch_pair(const Params& P, int grid, hipStream_t s);
 int pair_blocks_per_cu(int alphabet);
+hipError_t launch_block(const Params& P, int grid, hipStream_t s);
+int block_blocks_per_cu(int alphabet);
 hipError_t launch_general(const Params& P, int grid, hipStream_t s);
 hipError_t launch_combine(const Params& P, void* out, hipStream_t s);
 int wave_blocks_per_cu(int alphabet);

@@ -21,8 +21,10 @@
 //  * the window slides up by whole lanes when the band reaches its top, by as
 //    many as the dead lanes below the band allow; when the band is wider than
 //    the window the tile widens in place (C -> 2C, registers redistributed
-//    with ds_bpermute) up to C = 8 (512 cells); wider bands go to a workgroup
-//    tier with rings in device memory;
+//    with ds_bpermute) up to C = 8 (512 cells); wider bands go to a
+//    workgroup tier that spreads the window over the registers of four
+//    wavefronts (up to 2,048 cells), and beyond that to a tier with rings in
+//    device memory;
 //  * for C = 1 and 2, blocks of antidiagonals run in unrolled interior loops
 //    on the finite-lane masks, with the live-span count formed per block on
 //    the vector unit (fast_interior, fast_interior_multi);
@@ -168,20 +170,21 @@ __device__ __forceinline__ uint32_t load_word(const Src& S, int64_t w) {
 // (element e = source symbol start + dir * e), element e at position
 // e mod RS.  Extra words past the end mirror the first words so that reads
 // of a few consecutive words never wrap.
-template <int ALPHA>
-struct Ring;
+// RS elements, filled by NT threads (thread l writes the l-th piece of a
+// fill).
+template <int ALPHA, int RS_, int NT>
+struct RingT;
 
-template <>
-struct Ring<0> {  // 2-bit DNA
-  static constexpr int RS = 4096;          // elements
+template <int RS_, int NT>
+struct RingT<0, RS_, NT> {  // 2-bit DNA
+  static constexpr int RS = RS_;           // elements
   static constexpr int RW = RS / 16;       // words
   static constexpr int MIRROR = 1;
   static constexpr int WORDS = RW + MIRROR;
-  static constexpr int CH = 1024;          // elements per fill (16 per lane)
+  static constexpr int CH = 16 * NT;       // elements per fill (16 per thread)
 
   __device__ static void fill(uint32_t* ring, const Src& S, int64_t start,
-                              int dir, int c0) {
-    const int l = lane_id();
+                              int dir, int c0, int l) {
     int64_t e0 = (int64_t)c0 + 16 * l;
     uint32_t v;
     if (dir > 0) {
@@ -208,17 +211,16 @@ struct Ring<0> {  // 2-bit DNA
   }
 };
 
-template <>
-struct Ring<1> {  // one byte per code
-  static constexpr int RS = 2048;
+template <int RS_, int NT>
+struct RingT<1, RS_, NT> {  // one byte per code
+  static constexpr int RS = RS_;
   static constexpr int RW = RS / 4;
   static constexpr int MIRROR = 9;         // reads of up to 8 words
   static constexpr int WORDS = RW + MIRROR;
-  static constexpr int CH = 512;           // 8 per lane
+  static constexpr int CH = 8 * NT;        // elements per fill (8 per thread)
 
   __device__ static void fill(uint32_t* ring, const Src& S, int64_t start,
-                              int dir, int c0) {
-    const int l = lane_id();
+                              int dir, int c0, int l) {
     int64_t e0 = (int64_t)c0 + 8 * l;
     uint32_t v0, v1;
     if (dir > 0) {
@@ -260,6 +262,10 @@ struct Ring<1> {  // one byte per code
     }
   }
 };
+
+// The rings of one wavefront: 4,096 DNA codes or 2,048 byte codes.
+template <int ALPHA>
+using Ring = RingT<ALPHA, ALPHA == 0 ? 4096 : 2048, WAVE>;
 
 // ------------------------------------------------------------------ state
 // Scalar (wave-uniform) state of one extension.
@@ -311,7 +317,7 @@ __device__ __forceinline__ void cover_a(Ext& e, WaveLds<ALPHA>& w,
                                         const Src& P, int need_hi) {
   // make elements up to need_hi available (the ring keeps the RS below)
   while (e.loaded_a <= need_hi) {
-    Ring<ALPHA>::fill(w.ra, P, e.a_start, e.a_dir, e.loaded_a);
+    Ring<ALPHA>::fill(w.ra, P, e.a_start, e.a_dir, e.loaded_a, lane_id());
     e.loaded_a += Ring<ALPHA>::CH;
   }
   __builtin_amdgcn_wave_barrier();
@@ -321,7 +327,7 @@ template <int ALPHA>
 __device__ __forceinline__ void cover_b(Ext& e, WaveLds<ALPHA>& w,
                                         const Src& P, int need_hi) {
   while (e.loaded_b <= need_hi) {
-    Ring<ALPHA>::fill(w.rb, P, e.b_start, e.b_dir, e.loaded_b);
+    Ring<ALPHA>::fill(w.rb, P, e.b_start, e.b_dir, e.loaded_b, lane_id());
     e.loaded_b += Ring<ALPHA>::CH;
   }
   __builtin_amdgcn_wave_barrier();
@@ -1332,7 +1338,7 @@ __device__ __forceinline__ ItemSetup setup_item(const Params& P, int item) {
 
 __device__ __forceinline__ int tier_index(int C) {
   return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : C == 8 ? 3 : 4;
-}  // the general tier counts at index 5
+}  // the block tier counts at index 5, the device-memory tier at 6
 
 template <int ALPHA, int CMIN, int CMAX>
 __device__ __forceinline__ void run_item(const Params& P, const Src& S, int item,
@@ -1349,8 +1355,8 @@ __device__ __forceinline__ void run_item(const Params& P, const Src& S, int item
       r = start_tier<ALPHA, CMIN, CMAX>(e, w, tab, P, S, start, tier);
     }
     if (r == R_ESC) {
-      // band wider than the widest register window: restart the extension
-      // on the workgroup tier
+      // band wider than the widest register window of one wave: restart the
+      // extension on the block tier
       handed_on = true;
       if (lane_id() == 0) {
         const int slot = atomicAdd(P.counters + C_GEN_TAIL, 1);
@@ -1770,8 +1776,369 @@ __global__ __launch_bounds__(WAVE * WPB) void xd_pair_kernel(Params P) {
   }
 }
 
+// ------------------------------------------------------------------ block
+// Workgroup tier for bands wider than one wavefront's register window: the
+// paper's memory-restricted band (two antidiagonals of at most delta_b cells
+// kept in fast memory and updated in place, Sec. 3 and Alg. 1) with the
+// window spread over the registers of BT_WAVES wavefronts.  Thread
+// t = wave * 64 + lane holds window positions t*C .. t*C+C-1 of the current
+// antidiagonal (A) and the one before it (B); computing antidiagonal d
+// overwrites B in place.  Per antidiagonal the waves meet at one barrier:
+// before it each wave publishes, in LDS slots indexed by d mod 4, the value
+// of its top cell (the x-1 neighbour of the next wave's lane 0) and its part
+// of the reductions (its best cell if it beats T, its finite range); after it
+// every wave combines the BT_WAVES records into T, the end cell and the
+// finite range.  Sequences stream through workgroup LDS rings.  The window
+// slides by whole threads and widens in place (C = 4 -> 8, 1,024 -> 2,048
+// cells) through an LDS exchange buffer; a band wider than 2,048 cells moves
+// to the device-memory tier.
+constexpr int BT_WAVES = 4;
+constexpr int BT_NT = BT_WAVES * WAVE;
+
+template <int ALPHA>
+using BRing = RingT<ALPHA, ALPHA == 0 ? 8192 : 4096, BT_NT>;
+// a fill must never overwrite codes the 2,048-cell window still reads
+static_assert(BRing<0>::CH + 2048 - 1 <= BRing<0>::RS, "DNA block ring");
+static_assert(BRing<1>::CH + 2048 - 1 <= BRing<1>::RS, "byte block ring");
+
+template <int ALPHA>
+struct BlockLds {
+  uint32_t ra[BRing<ALPHA>::WORDS];
+  uint32_t rb[BRing<ALPHA>::WORDS];
+  int xa[BT_NT * 8], xb[BT_NT * 8];  // slide / widen exchange
+  int top[4][BT_WAVES];              // top cell of each wave, by d mod 4
+  int4 red[2][BT_WAVES];             // best value, its x, L, U; by d mod 2
+  int item;
+};
+
+// Make ring elements up to need_hi available (all threads fill, then meet).
+template <int ALPHA>
+__device__ __forceinline__ void bcover(int& loaded, uint32_t* ring,
+                                       const Src& S, int64_t start, int dir,
+                                       int need_hi) {
+  if (loaded > need_hi) return;  // (uniform)
+  do {
+    BRing<ALPHA>::fill(ring, S, start, dir, loaded, (int)threadIdx.x);
+    loaded += BRing<ALPHA>::CH;
+  } while (loaded <= need_hi);
+  __syncthreads();
+}
+
+// Query codes of a thread's C cells (they change only with the window base)
+// and the scores of its cells on one antidiagonal.
+template <int ALPHA, int C>
+struct BCodes;
+
+template <int C>
+struct BCodes<0, C> {
+  uint32_t qa;  // cell j's query code at bits 2j
+  __device__ void load(const uint32_t* ra, int base) {
+    qa = BRing<0>::read(ra, base + (int)threadIdx.x * C - 1);
+  }
+  // yb: target element of cell 0 (cell j takes yb - j)
+  __device__ void sims(const uint32_t* rb, int yb, const Params& P,
+                       const int*, int (&s)[C]) const {
+    const uint32_t bw = BRing<0>::read(rb, yb - C + 1);  // yb-C+1+k at 2k
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      s[j] = (((qa >> (2 * j)) ^ (bw >> (2 * (C - 1 - j)))) & 3u) ? P.mis_s
+                                                                  : P.mat_s;
+  }
+};
+
+template <int C>
+struct BCodes<1, C> {
+  static constexpr int NB = (C + 3) / 4;
+  int row[C];  // 32 * query code
+  __device__ void load(const uint32_t* ra, int base) {
+    uint32_t v[NB];
+    BRing<1>::read<NB>(ra, base + (int)threadIdx.x * C - 1, v);
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) << 5;
+  }
+  __device__ void sims(const uint32_t* rb, int yb, const Params&,
+                       const int* tab, int (&s)[C]) const {
+    uint32_t v[NB];
+    BRing<1>::read<NB>(rb, yb - C + 1, v);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = C - 1 - j;
+      s[j] = tab[row[j] + (int)((v[k >> 2] >> (8 * (k & 3))) & 31u)];
+    }
+  }
+};
+
+// Lane 63 of every wave publishes its top cells of A (antidiagonal d-1) and
+// B (d-2) after the window changed, then the workgroup meets.
+template <int ALPHA, int C>
+__device__ __forceinline__ void bpublish(const Ext& e, const int (&A)[C],
+                                         const int (&B)[C],
+                                         BlockLds<ALPHA>& L) {
+  const int wv = (int)threadIdx.x >> 6;
+  if (lane_id() == 63) {
+    L.top[(e.d - 1) & 3][wv] = A[C - 1];
+    L.top[(e.d - 2) & 3][wv] = B[C - 1];
+  }
+  __syncthreads();
+}
+
+// Window positions p <- p + sl*C (thread t takes thread t+sl's cells).
+template <int C>
+__device__ __forceinline__ void bslide(int (&A)[C], int (&B)[C], int* xa,
+                                       int* xb, int sl) {
+  const int t = (int)threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    xa[t * C + j] = A[j];
+    xb[t * C + j] = B[j];
+  }
+  __syncthreads();
+  const int src = t + sl;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    A[j] = src < BT_NT ? xa[src * C + j] : NEG;
+    B[j] = src < BT_NT ? xb[src * C + j] : NEG;
+  }
+}
+
+// C -> 2C cells per thread, same base (the upper half starts at -infinity).
+template <int C>
+__device__ __forceinline__ void bwiden(const int (&A)[C], const int (&B)[C],
+                                       int (&NA)[2 * C], int (&NB)[2 * C],
+                                       int* xa, int* xb) {
+  const int t = (int)threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    xa[t * C + j] = A[j];
+    xb[t * C + j] = B[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 2 * C; ++j) {
+    const int p = t * 2 * C + j;
+    NA[j] = p < BT_NT * C ? xa[p] : NEG;
+    NB[j] = p < BT_NT * C ? xb[p] : NEG;
+  }
+}
+
+// Antidiagonal e.d of the block tier (A: d-1, B: d-2 on entry; d, d-1 on
+// exit).  Returns R_CONT, R_DONE, R_CAP or R_ESC (the band needs a wider
+// window); every thread returns the same value.
+template <int ALPHA, int C>
+__device__ __forceinline__ int bstep(Ext& e, int (&A)[C], int (&B)[C],
+                                     BCodes<ALPHA, C>& cq, BlockLds<ALPHA>& L,
+                                     const int* tab, const Params& P,
+                                     const Src& S) {
+  constexpr int NC = BT_NT * C;
+  constexpr int LOG2C = C == 4 ? 2 : 3;
+  const int t = (int)threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int d = e.d;
+  const int lo = smax(smin(e.L1, e.L2 + 1), smax(0, d - e.n));
+  const int hi = smin(smax(e.U1, e.U2) + 1, smin(e.m, d));
+  const int width = hi - lo + 1;
+  if (width > 0) e.W += width;
+  if (P.band_cap > 0 && width > P.band_cap) return R_CAP;
+
+  bcover<ALPHA>(e.loaded_b, L.rb, S, e.b_start, e.b_dir, d - e.base - 1);
+  int s[C];
+  cq.sims(L.rb, d - e.base - t * C - 1, P, tab, s);
+  // x-1 neighbours of cell 0: the thread below, or for lane 0 the top cell
+  // of the wave below (published on the antidiagonal it belongs to)
+  const int fu = wv ? L.top[(d - 1) & 3][wv - 1] : NEG;
+  const int fd = wv ? L.top[(d - 2) & 3][wv - 1] : NEG;
+  const int up0 = wave_shr1(A[C - 1], fu);
+  const int dg0 = wave_shr1(B[C - 1], fd);
+  const int thr = smax(e.T - P.X - P.gap * d, THR_FLOOR);
+  const int pmin = d - e.n - e.base;
+  const uint32_t span = (uint32_t)(e.m - e.base - pmin);
+  int v[C];
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const int up = j ? A[j - 1] : up0;
+    const int dg = j ? B[j - 1] : dg0;
+    v[j] = max(max(up, A[j]), dg + s[j]);
+  }
+  uint64_t msk[C];
+  uint64_t any = 0;
+  int lm = NEG;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const bool f = v[j] >= thr && (uint32_t)(t * C + j - pmin) <= span;
+    v[j] = f ? v[j] : NEG;
+    msk[j] = ballot(f);
+    any |= msk[j];
+    lm = max(lm, v[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) { B[j] = A[j]; A[j] = v[j]; }
+  if (lane == 63) L.top[d & 3][wv] = A[C - 1];
+
+  // this wave's part of the reductions
+  const int Tv = e.T - P.gap * d;
+  const uint64_t imp = ballot(lm > Tv);
+  int wm = NEG, wx = 0x7fffffff;
+  if (imp) {
+    int l0;
+    if (__builtin_popcountll(imp) == 1) {
+      l0 = __builtin_ctzll(imp);
+      wm = __builtin_amdgcn_readlane(lm, l0);
+    } else {
+      wm = uni(wave_max(lm));
+      l0 = __builtin_ctzll(ballot(lm == wm));
+    }
+    int jf = C - 1;
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j)
+      if (A[j] == wm) jf = j;
+    wx = e.base + ((wv * 64 + l0) << LOG2C) + __builtin_amdgcn_readlane(jf, l0);
+  }
+  int wl = DEAD_L, wu = DEAD_U;
+  if (any) {
+    const int llo = __builtin_ctzll(any);
+    const int lhi = 63 - __builtin_clzll(any);
+    int jlo = 0, jhi = 0;
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j)
+      if ((msk[j] >> llo) & 1) jlo = j;
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if ((msk[j] >> lhi) & 1) jhi = j;
+    wl = e.base + ((wv * 64 + llo) << LOG2C) + jlo;
+    wu = e.base + ((wv * 64 + lhi) << LOG2C) + jhi;
+  }
+  if (lane == 0) L.red[d & 1][wv] = make_int4(wm, wx, wl, wu);
+  __syncthreads();
+  // all waves: best (lowest wave first on ties: its x is lower), range
+  int gm = NEG, gx = 0, gl = DEAD_L, gu = DEAD_U;
+#pragma unroll
+  for (int k = 0; k < BT_WAVES; ++k) {
+    const int4 r = L.red[d & 1][k];
+    if (r.x > gm) { gm = r.x; gx = r.y; }
+    gl = min(gl, r.z);
+    gu = max(gu, r.w);
+  }
+  gm = uni(gm); gx = uni(gx); gl = uni(gl); gu = uni(gu);
+  if (gm > Tv) {
+    e.T = gm + P.gap * d;
+    e.bx = gx;
+    e.by = d - gx;
+  }
+  const int L1 = e.L1, U1 = e.U1;
+  e.L2 = L1; e.U2 = U1;
+  e.L1 = gl; e.U1 = gu;
+  e.d = d + 1;
+  int r = R_CONT;
+  if ((gl > gu && L1 > U1) || d >= e.m + e.n) r = R_DONE;
+  if (r == R_CONT) {
+    // keep the next antidiagonal's band inside the window
+    const int hi_next = smin(smax(gu, U1) + 1, smin(e.m, d + 1));
+    if (hi_next > e.base + NC - 1) {
+      const int sl = (smin(gl, L1) - e.base) >> LOG2C;  // whole threads
+      if (sl < 1) {
+        r = R_ESC;
+      } else {
+        bslide<C>(A, B, L.xa, L.xb, sl);
+        e.base += sl << LOG2C;
+        bcover<ALPHA>(e.loaded_a, L.ra, S, e.a_start, e.a_dir,
+                      e.base + NC - 2);
+        cq.load(L.ra, e.base);
+        bpublish<ALPHA, C>(e, A, B, L);
+      }
+    }
+  }
+  make_uniform(e);
+  return r;
+}
+
+template <int ALPHA, int C, int CMAX>
+__device__ __forceinline__ int run_btier(Ext& e, int (&A)[C], int (&B)[C],
+                                         BlockLds<ALPHA>& L, const int* tab,
+                                         const Params& P, const Src& S,
+                                         int& tier_out) {
+  BCodes<ALPHA, C> cq;
+  bcover<ALPHA>(e.loaded_a, L.ra, S, e.a_start, e.a_dir,
+                e.base + BT_NT * C - 2);
+  cq.load(L.ra, e.base);
+  bpublish<ALPHA, C>(e, A, B, L);
+  int r;
+  do {
+    r = bstep<ALPHA, C>(e, A, B, cq, L, tab, P, S);
+  } while (r == R_CONT);
+  if constexpr (C < CMAX) {
+    if (r == R_ESC) {
+      int NA[2 * C], NB[2 * C];
+      bwiden<C>(A, B, NA, NB, L.xa, L.xb);
+      return run_btier<ALPHA, 2 * C, CMAX>(e, NA, NB, L, tab, P, S, tier_out);
+    }
+  }
+  tier_out = C;
+  return r;
+}
+
+// One extension on the block tier (all threads of the workgroup).
+template <int ALPHA>
+__device__ __forceinline__ void run_bitem(const Params& P, const Src& S,
+                                          int item, BlockLds<ALPHA>& L,
+                                          const int* tab) {
+  ItemSetup s = setup_item(P, item);
+  ItemResult res;
+  res.best = 0; res.x = 0; res.y = 0; res.status = s.status; res.cells = 0;
+  bool handed_on = false;
+  if (s.status == S_OK) {
+    Ext& e = s.e;
+    int r = R_DONE, tier = 4;
+    if (e.m + e.n != 0) {
+      int A[4], B[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) { A[j] = NEG; B[j] = NEG; }
+      if (threadIdx.x == 0) A[0] = 0;  // S(0,0) = 0 at window position 0
+      r = run_btier<ALPHA, 4, 8>(e, A, B, L, tab, P, S, tier);
+    }
+    if (r == R_ESC) {
+      // band wider than 2,048 cells: restart on the device-memory tier
+      handed_on = true;
+      if (threadIdx.x == 0) {
+        const int slot = atomicAdd(P.counters + C_DEV_TAIL, 1);
+        P.dev_queue[slot] = item;
+      }
+    } else if (r == R_CAP) {
+      res.status = S_BAND;
+    } else {
+      res.best = e.T; res.x = e.bx; res.y = e.by; res.cells = e.W;
+      if (threadIdx.x == 0) atomicAdd(P.counters + C_TIER0 + 5, 1);
+    }
+  }
+  if (!handed_on && threadIdx.x == 0) P.items[item] = res;
+}
+
+// Persistent block-tier kernel: one extension per workgroup at a time,
+// pulled from the queue the wave kernel (or the workgroup form) filled.
+template <int ALPHA>
+__global__ __launch_bounds__(BT_NT) void xd_block_kernel(Params P) {
+  __shared__ BlockLds<ALPHA> L;
+  __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
+  if constexpr (ALPHA == 1) {
+    for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
+      tab[i] = P.table[i];
+  }
+  const Src S = make_src(P);
+  const int tail = P.counters[C_GEN_TAIL];  // final: set by earlier kernels
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int h = tail > 0 ? atomicAdd(P.counters + C_GEN_HEAD, 1) : 0;
+      L.item = h < tail ? P.gen_queue[h] : -1;
+    }
+    __syncthreads();
+    const int item = uni(L.item);
+    if (item < 0) break;
+    run_bitem<ALPHA>(P, S, item, L, tab);
+  }
+}
+
 // ------------------------------------------------------------------ general
-// Workgroup-per-extension tier for bands wider than the register window:
+// Device-memory tier for bands wider than the block tier's 2,048 cells:
 // antidiagonals d, d-1, d-2 in three rings of GEN_CAP cells in device memory
 // (cell x at x mod GEN_CAP), every cell of [lo_d, hi_d] computed by the
 // GEN_THREADS threads of the block, reductions through LDS.
@@ -1799,8 +2166,9 @@ __global__ __launch_bounds__(GEN_THREADS) void xd_general_kernel(Params P) {
   for (;;) {
     __syncthreads();
     if (tid == 0) {
-      int h = atomicAdd(P.counters + C_GEN_HEAD, 1);
-      s_item = h < atomicAdd(P.counters + C_GEN_TAIL, 0) ? P.gen_queue[h] : -1;
+      const int tail = P.counters[C_DEV_TAIL];  // final: set by earlier kernels
+      const int h = tail > 0 ? atomicAdd(P.counters + C_DEV_HEAD, 1) : 0;
+      s_item = h < tail ? P.dev_queue[h] : -1;
     }
     __syncthreads();
     const int item = s_item;
@@ -1883,7 +2251,7 @@ __global__ __launch_bounds__(GEN_THREADS) void xd_general_kernel(Params P) {
     }
     if (res.status == S_OK) {
       res.best = T; res.x = bx; res.y = by; res.cells = W;
-      if (tid == 0) atomicAdd(P.counters + C_TIER0 + 5, 1);
+      if (tid == 0) atomicAdd(P.counters + C_TIER0 + 6, 1);
     } else if (res.status == S_BAND) {
       res.best = 0; res.x = 0; res.y = 0; res.cells = 0;
     }
@@ -2056,7 +2424,7 @@ __global__ __launch_bounds__(1024) void xd_scatter_kernel(const int32_t* seeds, 
 __global__ void xd_combine_kernel(Params P, void* out_v) {
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < C_REPORT; i += blockDim.x) {
-      if (i >= C_TIER0 && i < C_TIER0 + 6)
+      if (i >= C_TIER0 && i < C_TIER0 + N_TIERS)
         P.counters[C_REPORT + (i - C_TIER0)] = P.counters[i];
       P.counters[i] = 0;
     }
@@ -2102,6 +2470,8 @@ template __global__ void xd_wave_kernel<0, 8>(Params);
 template __global__ void xd_wave_kernel<1, 8>(Params);
 template __global__ void xd_pair_kernel<0>(Params);
 template __global__ void xd_pair_kernel<1>(Params);
+template __global__ void xd_block_kernel<0>(Params);
+template __global__ void xd_block_kernel<1>(Params);
 
 }  // namespace xd
 
@@ -2190,6 +2560,27 @@ int pair_blocks_per_cu(int alphabet) {
                 &nb, xd_pair_kernel<0>, WAVE * WPB, 0)
           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &nb, xd_pair_kernel<1>, WAVE * WPB, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_block(const Params& P, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (P.alphabet == 0)
+    hipLaunchKernelGGL((xd_block_kernel<0>), dim3(grid), dim3(BT_NT), 0, s, P);
+  else
+    hipLaunchKernelGGL((xd_block_kernel<1>), dim3(grid), dim3(BT_NT), 0, s, P);
+  return hipGetLastError();
+}
+
+int block_blocks_per_cu(int alphabet) {
+  int nb = 0;
+  hipError_t e =
+      alphabet == 0
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_block_kernel<0>, BT_NT, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_block_kernel<1>, BT_NT, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

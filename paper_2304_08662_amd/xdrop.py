@@ -260,8 +260,10 @@ class Context:
         return list(arr), int(nb.value)
 
     def last_stats(self) -> list:
-        arr = (ctypes.c_int64 * 6)()
-        _check(self.lib.xdrop_last_stats(self.handle, arr, 6),
+        """Extensions finished per tier: 1, 2, 4, 8 cells per lane, pair
+        kernel, block tier, device-memory tier."""
+        arr = (ctypes.c_int64 * 7)()
+        _check(self.lib.xdrop_last_stats(self.handle, arr, 7),
                "xdrop_last_stats")
         return list(arr)
 

@@ -35,6 +35,10 @@ struct dim3 {
 struct uint2 {
   uint32_t x, y;
 };
+struct int4 {
+  int x, y, z, w;
+};
+inline int4 make_int4(int x, int y, int z, int w) { return int4{x, y, z, w}; }
 
 namespace emu {
 struct Idx {

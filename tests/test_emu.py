@@ -144,3 +144,32 @@ def test_dna_100k_sample(emu):
     g = emu.run(b, product_scoring(scheme))
     assert not compare(g, oracle_run(b, scheme))
     assert emu.last_stats()[5] >= 2  # bands past 512 cells
+
+
+@pytest.mark.parametrize("alphabet", [4, 20])
+def test_block_tier_bands_512_to_2048_and_beyond(emu, alphabet):
+    """X -> infinity on unrelated pairs: bands grow to min(m, n) + 1 cells.
+    Lengths 520..2000 end on the block tier (four waves, 1,024 then 2,048
+    cells), one pair of 2,300 goes on to the device-memory tier; left and
+    right extensions, seeds inside the pairs."""
+    rng = np.random.default_rng([45, alphabet])
+    pairs = []
+    for L in (520, 700, 1000, 1500, 2000, 2300):
+        q = rng.integers(0, alphabet, L).astype(np.uint8)
+        t = rng.integers(0, alphabet, L + int(rng.integers(-30, 30))).astype(np.uint8)
+        pairs.append((q, t, 0, 0, 0))
+    for L in (1400, 2600):  # a seed in the middle: both sides wide
+        q = rng.integers(0, alphabet, L).astype(np.uint8)
+        t = rng.integers(0, alphabet, L).astype(np.uint8)
+        t[L // 2:L // 2 + 6] = q[L // 2:L // 2 + 6]
+        pairs.append((q, t, L // 2, L // 2, 6))
+    batch = make_batch(pairs, alphabet)
+    if alphabet == 4:
+        scheme = inputs.Scheme(4, 1, -1, -1, 2**31 - 1)
+    else:
+        scheme = inputs.Scheme(20, gap=-2, X=2**31 - 1,
+                               matrix=inputs.stand_in_substitution_matrix())
+    assert not compare(emu.run(batch, product_scoring(scheme)),
+                       oracle_run(batch, scheme))
+    stats = emu.last_stats()
+    assert stats[5] >= 5 and stats[6] >= 1, stats

@@ -117,10 +117,11 @@ def test_small_alphabet_bytes(runner):
     assert not compare(g, ref)
 
 
-HANG_REASON = ("skipped: a GPU run of this case (with the since removed "
-               "16-cell wave kernel) did not finish and the cause is not "
-               "shown; the case stays off the GPU (the CPU emulation of the "
-               "same kernels is bit-exact on the same batch)")
+HANG_REASON = ("skipped: a GPU run of this case (on a build with a since "
+               "removed 16-cell wave kernel) did not finish and no cause has "
+               "been shown, so the case stays off the GPU; the CPU build of "
+               "the kernel sources runs the same batch bit-exact for that "
+               "build and for this one (tests/test_emu.py)")
 
 
 @pytest.mark.parametrize("name,scale", [
@@ -212,6 +213,66 @@ def test_wide_bands_all_tiers(runner):
     assert not compare(g, ref)
     stats = runner.ctx.last_stats()
     assert stats[3] >= 1 and stats[5] >= 1, stats
+
+
+@pytest.mark.parametrize("alphabet", [4, 20])
+def test_block_tier_bands_512_to_2048_and_beyond(runner, alphabet):
+    """X -> infinity on unrelated pairs (bands grow to min(m, n) + 1 cells):
+    lengths 520..2000 end on the block tier (four waves, 1,024 then 2,048
+    cells), pairs past 2,048 cells go on to the device-memory tier."""
+    rng = np.random.default_rng([45, alphabet])
+    pairs = []
+    for L in (520, 700, 1000, 1500, 2000, 2300):
+        q = rng.integers(0, alphabet, L).astype(np.uint8)
+        t = rng.integers(0, alphabet, L + int(rng.integers(-30, 30))).astype(np.uint8)
+        pairs.append((q, t, 0, 0, 0))
+    for L in (1400, 2600):  # a seed in the middle: both sides wide
+        q = rng.integers(0, alphabet, L).astype(np.uint8)
+        t = rng.integers(0, alphabet, L).astype(np.uint8)
+        t[L // 2:L // 2 + 6] = q[L // 2:L // 2 + 6]
+        pairs.append((q, t, L // 2, L // 2, 6))
+    batch = make_batch(pairs, alphabet)
+    if alphabet == 4:
+        scheme = inputs.Scheme(4, 1, -1, -1, 2**31 - 1)
+    else:
+        scheme = inputs.Scheme(20, gap=-2, X=2**31 - 1,
+                               matrix=inputs.stand_in_substitution_matrix())
+    ref = oracle_run(batch, scheme)
+    assert not compare(runner.run(batch, scheme), ref)
+    stats = runner.ctx.last_stats()
+    assert stats[5] >= 5 and stats[6] >= 1, stats
+    # every extension on the block tier from the first antidiagonal
+    from paper_2304_08662_amd import xdrop
+    assert not compare(runner.run(batch, scheme, xdrop.options(variant=2)), ref)
+
+
+def test_long_byte_codes_wrap_rings(runner):
+    """Byte-coded pairs of 3,000-10,000 codes: every extension passes the
+    2,048-code ring of its wave (and the 4,096-code ring of the block tier)
+    several times; related and unrelated pairs, left and right extensions,
+    seeds near both ends, X = 49 and X = 400 (windows widen to 8 cells per
+    lane and onto the block tier)."""
+    rng = np.random.default_rng(42)
+    M = inputs.stand_in_substitution_matrix()
+    pairs = []
+    for i in range(16):
+        L = int(rng.integers(3000, 10001))
+        q = rng.integers(0, 20, L).astype(np.uint8)
+        if i % 2 == 0:
+            t, _ = inputs.mutate(rng, q, 0.2, 0.03, 0.03, 20)
+        else:
+            t = rng.integers(0, 20, int(rng.integers(3000, 10001))).astype(np.uint8)
+        k = 6
+        where = [0.02, 0.5, 0.98][i % 3]
+        qp = int(where * (len(q) - k))
+        tp = min(int(where * (len(t) - k)), len(t) - k)
+        t = t.copy()
+        t[tp:tp + k] = q[qp:qp + k]
+        pairs.append((q, t, qp, tp, k))
+    batch = make_batch(pairs, 20)
+    for X in (49, 400):
+        scheme = inputs.Scheme(20, gap=-2, X=X, matrix=M)
+        assert not compare(runner.run(batch, scheme), oracle_run(batch, scheme)), X
 
 
 def test_statuses(runner):
