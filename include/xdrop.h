@@ -54,6 +54,8 @@ typedef enum {
     XDROP_E_SYMBOL = -6,   /* per seed: a code >= alphabet_size */
     XDROP_BAND_OVERFLOW = -7, /* per seed: band wider than opts->band_cap,
                                  or than 65536 cells (device-memory tier) */
+    XDROP_E_SCRATCH = -8,  /* batch larger than the fixed scratch of
+                              xdrop_extend_batch_noalloc */
     XDROP_PENDING = 1      /* serving: request not finished yet */
 } xdrop_status;
 
@@ -155,6 +157,28 @@ int xdrop_extend_batch(xdrop_ctx *ctx, const uint8_t *d_seqs,
                        const xdrop_scoring *scoring,
                        const xdrop_options *opts, xdrop_result *d_results,
                        void *stream);
+
+/* Allocation-free variant of xdrop_extend_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and per-seed
+ * statuses as xdrop_extend_batch; it calls no hipMalloc/hipFree and creates
+ * no events (phase timing is off for it).  Its counters, queues, result slots
+ * and device-memory tier rings live in one fixed 16 MiB device array per GPU
+ * (held until the process ends), so a batch may hold at most
+ * XDROP_NOALLOC_MAX_SEEDS seeds over at most XDROP_NOALLOC_MAX_SEQS
+ * sequences (else XDROP_E_SCRATCH, nothing launched), and at most 4
+ * extensions with bands wider than 2,048 cells run at once.  Every call on a
+ * GPU shares that array: calls that overlap on one GPU (other streams, other
+ * contexts or threads) race and must be ordered by the caller.  Each call
+ * clears the counters it needs before use. */
+#define XDROP_NOALLOC_MAX_SEEDS 65536
+#define XDROP_NOALLOC_MAX_SEQS 1048576
+int xdrop_extend_batch_noalloc(xdrop_ctx *ctx, const uint8_t *d_seqs,
+                               const int64_t *d_offsets, int32_t n_seqs,
+                               const xdrop_seed *d_seeds, int32_t n_seeds,
+                               const xdrop_scoring *scoring,
+                               const xdrop_options *opts,
+                               xdrop_result *d_results, void *stream);
 
 /* Autotune the launch parameters on a sample batch (same arguments as
  * xdrop_extend_batch; d_results is scratch) by timing every candidate

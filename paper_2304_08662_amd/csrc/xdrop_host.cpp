@@ -42,6 +42,9 @@ struct xdrop_ctx {
   int32_t* counters = nullptr;
   int32_t* gen_scratch = nullptr;
   int gen_slots = 32;
+  int32_t* last_counters = nullptr;  // counters of the last batch
+  char* scratch = nullptr;  // the device's fixed scratch (allocation-free
+                            // entry point)
   int pair_blocks_per_cu[2] = {0, 0};
   int block_blocks_per_cu[2] = {0, 0};
   int blocks_per_cu[2] = {0, 0};  // [alphabet]
@@ -208,11 +211,25 @@ int ensure_workspace(xdrop_ctx* c, size_t bytes, hipStream_t st) {
   return XDROP_OK;
 }
 
-// Enqueue the whole launch sequence of one batch on `st`.
+// Device buffers one batch runs on: the context's workspace, or the fixed
+// scratch of the allocation-free entry point.
+struct Workspace {
+  char* ws;              // Layout regions (items, order, queues, symbols)
+  int32_t* counters;     // C_COUNT counters
+  int32_t* gen_scratch;  // device-memory tier rings, gen_slots of them
+  int gen_slots;
+  bool reset;            // zero the counters first (they hold another
+                         // call's values)
+};
+
+// Enqueue the whole launch sequence of one batch on `st`.  fixed == nullptr:
+// the context's workspace, grown on demand; otherwise the given buffers,
+// and nothing is allocated.
 int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
             int32_t n_seqs, const xdrop_seed* d_seeds, int32_t n_seeds,
             const xdrop_scoring* sc, const xdrop_options* opts,
-            xdrop_result* d_results, hipStream_t st) {
+            xdrop_result* d_results, hipStream_t st,
+            const Workspace* fixed = nullptr) {
   Params P;
   std::memset(&P, 0, sizeof(P));
   int rc = fill_scoring(sc, P);
@@ -226,19 +243,27 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   xdrop_options o = resolve(c, sc, opts);
   const int32_t n_items = 2 * n_seeds;
   Layout L = layout(n_items, n_seqs);
-  rc = ensure_workspace(c, L.total, st);
-  if (rc != XDROP_OK) return rc;
-  char* ws = (char*)c->ws;
+  Workspace W;
+  if (fixed) {
+    W = *fixed;
+  } else {
+    rc = ensure_workspace(c, L.total, st);
+    if (rc != XDROP_OK) return rc;
+    W = Workspace{(char*)c->ws, c->counters, c->gen_scratch, c->gen_slots,
+                  false};
+  }
+  char* ws = W.ws;
+  c->last_counters = W.counters;
 
   P.seqs = (const uint32_t*)d_seqs;
   P.offsets = d_offsets;
   P.seeds = (const int32_t*)d_seeds;
   P.items = (ItemResult*)(ws + L.items);
-  P.counters = c->counters;
+  P.counters = W.counters;
   P.gen_queue = (int32_t*)(ws + L.gen_q);
   P.dev_queue = (int32_t*)(ws + L.dev_q);
   P.esc_queue = (int32_t*)(ws + L.esc_q);
-  P.gen_scratch = c->gen_scratch;
+  P.gen_scratch = W.gen_scratch;
   P.n_seqs = n_seqs;
   P.n_seeds = n_seeds;
   P.n_items = n_items;
@@ -256,7 +281,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   }
   P.chunk = o.chunk;
   P.band_cap = o.band_cap;
-  P.gen_slots = c->gen_slots;
+  P.gen_slots = W.gen_slots;
   if (o.variant == XDROP_VARIANT_AUTO) {
     // a batch within one wave of the persistent grid starts every extension
     // at once: the plain form (one launched wave per extension) then does
@@ -271,7 +296,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   P.flags = plain ? F_PLAIN : 0;
 
   hipEvent_t* ev = nullptr;
-  if (c->timing) {
+  if (c->timing && !fixed) {  // (event creation is left to the other path)
     if (c->ev_used == c->ev_sets.size()) {
       std::array<hipEvent_t, 6> set{};
       for (auto& e : set) HIP_OK(hipEventCreate(&e));
@@ -281,6 +306,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   }
   const bool timed = ev != nullptr;
   if (timed) HIP_OK(hipEventRecord(ev[0], st));
+  if (W.reset) HIP_OK(launch_reset(W.counters, st));
   // (the counters were left zero by the previous batch's combine kernel)
   if (P.alphabet == 1) {
     P.seq_bad = (const uint8_t*)(ws + L.bad);
@@ -290,7 +316,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   }
   if (o.order == 0 && !plain) {
     int32_t* ord = (int32_t*)(ws + L.order);
-    HIP_OK(launch_order(P.seeds, d_offsets, n_seqs, n_items, c->counters, ord,
+    HIP_OK(launch_order(P.seeds, d_offsets, n_seqs, n_items, W.counters, ord,
                         c->num_cu, st));
     P.order = ord;
     P.flags |= F_ORDERED;
@@ -306,7 +332,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   if (timed) HIP_OK(hipEventRecord(ev[1], st));
   if (o.variant == XDROP_VARIANT_WORKGROUP) {
     // every extension on the workgroup tier
-    HIP_OK(launch_fill_queue(P.order, n_items, P.gen_queue, c->counters,
+    HIP_OK(launch_fill_queue(P.order, n_items, P.gen_queue, W.counters,
                              C_GEN_TAIL, st));
     if (timed) HIP_OK(hipEventRecord(ev[2], st));
     if (timed) HIP_OK(hipEventRecord(ev[3], st));
@@ -340,7 +366,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   if (!c->block_blocks_per_cu[a]) c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
   HIP_OK(launch_block(P, std::min(c->num_cu * c->block_blocks_per_cu[a],
                                   n_items), st));
-  HIP_OK(launch_general(P, c->gen_slots, st));
+  HIP_OK(launch_general(P, W.gen_slots, st));
   if (timed) HIP_OK(hipEventRecord(ev[4], st));
   HIP_OK(launch_combine(P, d_results, st));
   if (timed) {
@@ -365,6 +391,9 @@ const char* xdrop_strerror(int s) {
     case XDROP_E_SYMBOL: return "symbol outside the alphabet";
     case XDROP_BAND_OVERFLOW: return "band wider than the cap";
     case XDROP_PENDING: return "pending";
+    case XDROP_E_SCRATCH:
+      return "batch larger than the fixed scratch of the allocation-free "
+             "entry point";
     default: return "unknown status";
   }
 }
@@ -388,6 +417,21 @@ int xdrop_ctx_create(int device, xdrop_ctx** out) {
     return XDROP_E_DEVICE;
   }
   c->num_cu = prop.multiProcessorCount;
+  // occupancy of every kernel form, queried once here (the launch paths then
+  // make no runtime queries, under graph capture or otherwise)
+  for (int a = 0; a < 2; ++a) {
+    c->blocks_per_cu[a] = wave_blocks_per_cu(a);
+    c->pair_blocks_per_cu[a] = pair_blocks_per_cu(a);
+    c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
+  }
+  // the address of this device's fixed scratch, for the allocation-free
+  // entry point
+  void* sp = nullptr;
+  if (noalloc_scratch(device, &sp) != hipSuccess || !sp) {
+    delete c;
+    return XDROP_E_DEVICE;
+  }
+  c->scratch = (char*)sp;
   *out = c;
   return XDROP_OK;
 }
@@ -420,6 +464,31 @@ int xdrop_extend_batch(xdrop_ctx* c, const uint8_t* d_seqs,
                  opts, d_results, (hipStream_t)stream);
 }
 
+int xdrop_extend_batch_noalloc(xdrop_ctx* c, const uint8_t* d_seqs,
+                               const int64_t* d_offsets, int32_t n_seqs,
+                               const xdrop_seed* d_seeds, int32_t n_seeds,
+                               const xdrop_scoring* scoring,
+                               const xdrop_options* opts,
+                               xdrop_result* d_results, void* stream) {
+  if (!c) return XDROP_E_INVALID;
+  if (c->sticky != XDROP_OK) return c->sticky;
+  if (n_seeds < 0 || n_seqs < 0) return XDROP_E_INVALID;
+  if (n_seeds > XDROP_NOALLOC_MAX_SEEDS || n_seqs > XDROP_NOALLOC_MAX_SEQS)
+    return XDROP_E_SCRATCH;
+  // scratch: counters | device-memory tier rings | Layout regions
+  constexpr size_t CNT = 4096;
+  constexpr int SLOTS = 4;
+  constexpr size_t RINGS = (size_t)SLOTS * 3 * GEN_CAP * sizeof(int32_t);
+  const Layout L = layout(2 * n_seeds, n_seqs);
+  if (CNT + RINGS + L.total > NOALLOC_BYTES) return XDROP_E_SCRATCH;
+  static_assert(C_COUNT * sizeof(int32_t) <= CNT, "counter block");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
+  const Workspace W{c->scratch + CNT + RINGS, (int32_t*)c->scratch,
+                    (int32_t*)(c->scratch + CNT), SLOTS, true};
+  return enqueue(c, d_seqs, d_offsets, n_seqs, d_seeds, n_seeds, scoring,
+                 opts, d_results, (hipStream_t)stream, &W);
+}
+
 int xdrop_ctx_set_timing(xdrop_ctx* c, int32_t on) {
   if (!c) return XDROP_E_INVALID;
   (void)hipSetDevice(c->device);
@@ -448,8 +517,8 @@ int xdrop_last_timing(xdrop_ctx* c, float* ms, int32_t n,
 int xdrop_last_stats(xdrop_ctx* c, int64_t* counts, int32_t n_counts) {
   if (!c || !counts || n_counts < 0) return XDROP_E_INVALID;
   int32_t h[C_COUNT] = {0};
-  if (c->counters) {
-    if (hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost) !=
+  if (c->last_counters) {
+    if (hipMemcpy(h, c->last_counters, sizeof(h), hipMemcpyDeviceToHost) !=
         hipSuccess)
       return fail(c, hipErrorUnknown);
   }

@@ -101,6 +101,8 @@ constexpr int N_TIERS = 7;
 #include <stddef.h>
 
 namespace xd {
+constexpr size_t NOALLOC_BYTES = (size_t)16 << 20;
+hipError_t noalloc_scratch(int device, void** out);
 hipError_t launch_reset(int32_t* counters, hipStream_t s);
 hipError_t launch_validate(const uint8_t* seqs, const int64_t* offsets,
                            int32_t n_seqs, const int32_t* seeds,

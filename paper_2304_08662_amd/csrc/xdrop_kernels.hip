@@ -37,6 +37,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "xdrop_internal.h"
@@ -2478,6 +2479,28 @@ template __global__ void xd_block_kernel<1>(Params);
 // ==================================================================== host
 // Launch wrappers used by the C ABI (xdrop_host.cpp).
 namespace xd {
+
+// Fixed scratch of the allocation-free entry point: counters, queues, result
+// slots and device-memory tier rings of one batch.  Every GPU the library
+// runs on holds one copy until the process ends.
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
+// Its device address on `device` (the current device), looked up once per
+// device; host code passes this address, never the array's name.
+hipError_t noalloc_scratch(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 __global__ void xd_fill_queue_kernel(const int32_t* order, int32_t n,
                                      int32_t* queue, int32_t* counters,

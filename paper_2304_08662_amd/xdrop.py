@@ -24,6 +24,9 @@ E_DEVICE = -4
 E_BUDGET = -5
 E_SYMBOL = -6
 BAND_OVERFLOW = -7
+E_SCRATCH = -8
+NOALLOC_MAX_SEEDS = 65536
+NOALLOC_MAX_SEQS = 1048576
 PENDING = 1
 
 DNA2 = 0
@@ -88,6 +91,7 @@ class ServerOpts(ctypes.Structure):
 
 
 EXPORTS = ["xdrop_ctx_create", "xdrop_ctx_destroy", "xdrop_extend_batch",
+           "xdrop_extend_batch_noalloc",
            "xdrop_ctx_set_timing", "xdrop_last_timing",
            "xdrop_autotune", "xdrop_load_tuning", "xdrop_extend_batch_graph",
            "xdrop_last_stats", "xdrop_server_create", "xdrop_server_submit",
@@ -115,6 +119,7 @@ def load_library(path: str = LIB_PATH):
                   ctypes.POINTER(Options), vp, vp]
     lib.xdrop_extend_batch.argtypes = batch_args
     lib.xdrop_extend_batch_graph.argtypes = batch_args
+    lib.xdrop_extend_batch_noalloc.argtypes = batch_args
     lib.xdrop_autotune.argtypes = [vp, vp, vp, i32, vp, i32,
                                    ctypes.POINTER(Scoring), vp, vp,
                                    ctypes.c_char_p, ctypes.POINTER(Options)]
@@ -214,13 +219,17 @@ class Context:
 
     def extend_batch(self, seqs, offsets, seeds, scoring: ScoringSpec,
                      results, opts: Options | None = None, stream=None,
-                     graph: bool = False):
+                     graph: bool = False, noalloc: bool = False):
         """Enqueue the batch.  seqs: uint8 device tensor (packed stream),
         offsets: int64 (n_seqs+1), seeds: int32 (n, 5), results: any device
-        tensor of n * 48 bytes.  Returns the status (raises on error)."""
+        tensor of n * 48 bytes.  graph: record / replay a HIP graph;
+        noalloc: the allocation-free entry point.  Returns the status
+        (raises on error)."""
         sc = scoring.c()
         n_seeds = int(seeds.shape[0]) if seeds.dim() > 1 else int(seeds.numel() // 5)
-        f = self.lib.xdrop_extend_batch_graph if graph else self.lib.xdrop_extend_batch
+        f = (self.lib.xdrop_extend_batch_noalloc if noalloc else
+             self.lib.xdrop_extend_batch_graph if graph else
+             self.lib.xdrop_extend_batch)
         rc = f(self.handle, _ptr(seqs), _ptr(offsets), int(offsets.numel() - 1),
                _ptr(seeds), n_seeds, ctypes.byref(sc),
                ctypes.byref(opts) if opts is not None else None,

@@ -26,6 +26,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static thread_local
+#define __align__(n) __attribute__((aligned(n)))
 #define HIP_SYMBOL(s) (&(s))
 
 struct dim3 {

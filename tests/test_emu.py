@@ -173,3 +173,24 @@ def test_block_tier_bands_512_to_2048_and_beyond(emu, alphabet):
                        oracle_run(batch, scheme))
     stats = emu.last_stats()
     assert stats[5] >= 5 and stats[6] >= 1, stats
+
+
+def test_noalloc_equals_extend_batch_twice(emu):
+    """The allocation-free entry point on the CPU build: identical to
+    xdrop_extend_batch on two calls in a row, the second smaller."""
+    rng = np.random.default_rng(60)
+    pairs = _fuzz(rng, 80, 4, 900, related_p=0.5)
+    for L in (2300,):
+        pairs.append((rng.integers(0, 4, L).astype(np.uint8),
+                      rng.integers(0, 4, L).astype(np.uint8), 0, 0, 0))
+    big = make_batch(pairs, 4)
+    small = make_batch(_fuzz(rng, 20, 20, 400), 20)
+    for batch, scheme in (
+            (big, inputs.Scheme(4, 1, -1, -1, 2**31 - 1)),
+            (small, inputs.Scheme(20, gap=-2, X=49,
+                                  matrix=inputs.stand_in_substitution_matrix()))):
+        sc = product_scoring(scheme)
+        ref = emu.run(batch, sc)
+        got = emu.run(batch, sc, noalloc=True)
+        assert not compare(got, ref)
+        assert not compare(got, oracle_run(batch, scheme))

@@ -37,10 +37,12 @@ class EmuLib:
         args = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(xdrop.Scoring),
                 ctypes.POINTER(xdrop.Options), vp, vp]
         lib.xdrop_extend_batch.argtypes = args
+        lib.xdrop_extend_batch_noalloc.argtypes = args
         lib.xdrop_last_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                          i32]
         for f in ("xdrop_ctx_create", "xdrop_ctx_destroy",
-                  "xdrop_extend_batch", "xdrop_last_stats"):
+                  "xdrop_extend_batch", "xdrop_extend_batch_noalloc",
+                  "xdrop_last_stats"):
             getattr(lib, f).restype = ctypes.c_int
         self.lib = lib
         h = ctypes.c_void_p()
@@ -53,7 +55,8 @@ class EmuLib:
             self.lib.xdrop_ctx_destroy(self.ctx)
             self.ctx = None
 
-    def run(self, batch, scoring: "xdrop.ScoringSpec", opts=None):
+    def run(self, batch, scoring: "xdrop.ScoringSpec", opts=None,
+            noalloc=False):
         packed = batch.packed() if batch.alphabet == 4 and \
             scoring.alphabet == xdrop.DNA2 else \
             np.ascontiguousarray(batch.codes, dtype=np.uint8)
@@ -66,7 +69,9 @@ class EmuLib:
         res = np.zeros(max(n, 1), dtype=xdrop.RESULT_DTYPE)
         res.view(np.int32)[:] = -12345
         sc = scoring.c()
-        rc = self.lib.xdrop_extend_batch(
+        f = (self.lib.xdrop_extend_batch_noalloc if noalloc
+             else self.lib.xdrop_extend_batch)
+        rc = f(
             self.ctx, packed.ctypes.data, offs.ctypes.data, len(offs) - 1,
             sd.ctypes.data, n, ctypes.byref(sc),
             ctypes.byref(opts) if opts is not None else None,

@@ -40,7 +40,7 @@ class Runner:
         return self.xdrop.to_device(packed, batch.offsets, batch.seeds)
 
     def run(self, batch, scheme, opts=None, graph=False, dev=None,
-            alphabet=None):
+            alphabet=None, noalloc=False):
         torch, xdrop = self.torch, self.xdrop
         sc = product_scoring(scheme)
         if alphabet is not None:
@@ -54,7 +54,8 @@ class Runner:
         self.stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.stream):
             self.ctx.extend_batch(d_seqs, d_offs, d_seeds, sc, res, opts,
-                                  stream=self.stream, graph=graph)
+                                  stream=self.stream, graph=graph,
+                                  noalloc=noalloc)
         self.stream.synchronize()
         return xdrop.results_to_numpy(res, n)
 
