@@ -28,7 +28,7 @@ OPS_PER_CELL = 9
 
 METRIC = ("GCUPS + alignments/s (int32, bit-exact) and p50/p99 latency in "
           "serving loop")
-DEFAULT_WORKLOAD = "dna-1k"
+DEFAULT_WORKLOAD = "protein-500k"
 
 
 def log(*a):
@@ -182,6 +182,95 @@ def serving_run(xdrop, n_requests: int, rates=(0.8,), budget=64 << 30):
     return out
 
 
+def load_workload(name: str, scale: float):
+    """The seeded workload, kept in /tmp between runs on one host (the
+    generator is deterministic; the protein one takes tens of seconds)."""
+    from paper_2304_08662_amd import inputs
+    path = os.path.join(os.environ.get("TMPDIR", "/tmp"),
+                        f"xdrop_bench_{name}_{scale}.npz")
+    if os.path.exists(path):
+        z = np.load(path)
+        batch = inputs.Batch(z["codes"], z["offsets"], z["seeds"],
+                             int(z["alphabet"]))
+        _, scheme = inputs.workload(name, 1e-9)  # (one pair: the scoring)
+        return batch, scheme
+    batch, scheme = inputs.workload(name, scale)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, codes=batch.codes, offsets=batch.offsets, seeds=batch.seeds,
+             alphabet=batch.alphabet)
+    os.replace(tmp, path)
+    return batch, scheme
+
+
+UNMEASURED = {
+    "dna-100k": ("not run on the GPU: a GPU run of its parity case (on a "
+                 "build with a since removed 16-cell wave kernel) did not "
+                 "finish and no cause has been shown, so the case stays off "
+                 "the GPU; its results are checked on the CPU build of the "
+                 "kernel sources only"),
+}
+
+
+def time_steps(ctx, args_dev, sc, res, opts, stream, steps, warmup):
+    """Mean ms per step over `steps` batches (HIP events on the launch
+    stream, bracketed by device synchronisation), after `warmup`."""
+    import torch
+    for _ in range(warmup):
+        ctx.extend_batch(*args_dev, sc, res, opts, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.extend_batch(*args_dev, sc, res, opts, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps
+
+
+def phase_times(ctx, args_dev, sc, res, opts, stream, steps):
+    """Per-phase ms (HIP events on the launch stream around each kernel of
+    the sequence), averaged over `steps` further batches."""
+    ctx.set_timing(True)
+    for _ in range(steps):
+        ctx.extend_batch(*args_dev, sc, res, opts, stream=stream)
+    stream.synchronize()
+    phase_sum, nb = ctx.last_timing()
+    ctx.set_timing(False)
+    assert nb == steps
+    return np.array(phase_sum) / nb
+
+
+def other_workload(xdrop, ctx, name, steps, stream):
+    """Automatic and plain-form step times of another workload."""
+    from paper_2304_08662_amd import inputs
+    batch, scheme = load_workload(name, 1.0)
+    n = len(batch.seeds)
+    packed = batch.packed() if batch.alphabet == 4 else batch.codes
+    dev = xdrop.to_device(packed, batch.offsets, batch.seeds)
+    res = xdrop.result_buffer(n)
+    sc = scoring_for(xdrop, scheme)
+    stream.wait_stream(__import__("torch").cuda.current_stream())
+    ms, _ = time_steps(ctx, dev, sc, res, None, stream, steps, 2)
+    got = xdrop.results_to_numpy(res, n)
+    assert (got["status"] == 0).all()
+    plain_ms, _ = time_steps(ctx, dev, sc, res, xdrop.options(variant=3),
+                             stream, steps, 1)
+    o = ctx.resolve_options(sc, n)
+    live = int(got["cells"].sum())
+    return {"ms_per_step": round(ms, 4),
+            "gcups": round(batch.gcups_cells() / (ms / 1e3) / 1e9, 1),
+            "alignments_per_s": round(n / (ms / 1e3), 1),
+            "live_gcups": round(live / (ms / 1e3) / 1e9, 1),
+            "form": {"variant": o.variant, "tile": o.tile, "chunk": o.chunk},
+            "plain_ms_per_step": round(plain_ms, 4),
+            "seeds": n, "X": scheme.X}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,9 +285,15 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--autotune", action="store_true",
-                    help="tune variant / tile / chunk on this batch first; "
-                         "the timed steps then use the tuned choice")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the automatic choice without tuning first "
+                         "(by default the launch form, tile and chunk are "
+                         "tuned on the batch before the timed steps)")
+    ap.add_argument("--tuning", default=None, metavar="PATH",
+                    help="tuning cache (JSON lines): read instead of tuning "
+                         "if it exists, else written by the tuning run")
+    ap.add_argument("--others", default="dna-1k,dna-tail",
+                    help="other workloads timed after the headline one")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB five "
                          "times (reference for HBM byte counters) and exit")
@@ -207,6 +302,9 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU "
               "path (the work would shard by seeds, with no exchange "
               "between GPUs)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in UNMEASURED:
+        print(f"{args.workload}: {UNMEASURED[args.workload]}", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -223,72 +321,56 @@ def main():
                           nbytes, "copies": 5}), flush=True)
         return
     log(f"generating {args.workload} x{args.scale}")
-    batch, scheme = inputs.workload(args.workload, args.scale)
+    batch, scheme = load_workload(args.workload, args.scale)
     n = len(batch.seeds)
     packed = batch.packed() if batch.alphabet == 4 else batch.codes
-    d_seqs, d_offs, d_seeds = xdrop.to_device(packed, batch.offsets,
-                                              batch.seeds)
+    dev = xdrop.to_device(packed, batch.offsets, batch.seeds)
     res = xdrop.result_buffer(n)
     ctx = xdrop.Context(0)
     sc = scoring_for(xdrop, scheme)
-    opts = xdrop.options(args.variant, args.tile, args.chunk)
+    given = args.variant or args.tile or args.chunk
+    opts = xdrop.options(args.variant, args.tile, args.chunk) if given else None
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     tuned = None
-    if args.autotune:
+    if args.tuning and os.path.exists(args.tuning) and not given:
+        ctx.load_tuning(args.tuning)
+        o = ctx.resolve_options(sc, n)
+        tuned = {"variant": o.variant, "tile": o.tile, "chunk": o.chunk,
+                 "from": args.tuning}
+    elif not args.no_autotune and not given:
         log("autotune")
-        best = ctx.autotune(d_seqs, d_offs, d_seeds, sc, res, stream=stream)
+        t0 = time.perf_counter()
+        best = ctx.autotune(*dev, sc, res, cache_path=args.tuning,
+                            stream=stream)
         stream.synchronize()
         tuned = {"variant": best.variant, "tile": best.tile,
-                 "chunk": best.chunk}
+                 "chunk": best.chunk,
+                 "seconds": round(time.perf_counter() - t0, 2)}
         log(f"tuned {tuned}")
-        opts = None  # automatic: the context now holds the tuned choice
-    def step():
-        ctx.extend_batch(d_seqs, d_offs, d_seeds, sc, res, opts,
-                         stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    stream.synchronize()
-    log("warm")
-    # the timed steps carry no per-phase events (each event record is a
-    # marker packet on the stream and costs microseconds of its own)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    e1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step, wall_step = time_steps(ctx, dev, sc, res, opts, stream,
+                                    args.steps, args.warmup)
     got = xdrop.results_to_numpy(res, n)
     assert (got["status"] == 0).all(), "unexpected per-seed status"
     live = int(got["cells"].sum())
     cells = batch.gcups_cells()
     gcups = cells / (ms_step / 1e3) / 1e9
-    # per-phase durations (HIP events on the launch stream around each
-    # kernel of the sequence) from a second run of the same steps
-    ctx.set_timing(True)
-    for _ in range(args.steps):
-        step()
-    stream.synchronize()
-    phase_sum, nb = ctx.last_timing()
-    ctx.set_timing(False)
-    assert nb == args.steps
-    phase = np.array(phase_sum) / nb
-    # (1) the first extension kernel: the pair kernel in the default form,
-    # else the wave kernel; (2) the wave kernel on the extensions the pair
-    # kernel handed on
+    phase = phase_times(ctx, dev, sc, res, opts, stream, args.steps)
+    # the plain form (one launched wave per extension, no queue) on the same
+    # batch: the baseline the persistent form is compared with
+    plain_ms, _ = time_steps(ctx, dev, sc, res, xdrop.options(variant=3),
+                             stream, max(2, args.steps // 2), 1)
+    form = ctx.resolve_options(sc, n, opts)
+    # (1) the first extension kernel: the pair kernel in the pair form, else
+    # the wave kernel; (2) the wave kernel on the extensions the pair kernel
+    # handed on
     names = ["prep", "extend", "extend_handed_on", "workgroup", "combine"]
     dom = int(np.argmax(phase))
     achieved = OPS_PER_CELL * live / (phase[dom] / 1e3) / 1e12
     stats = ctx.last_stats()
-    log(f"step {ms_step:.3f} ms  wall/step {wall / args.steps * 1e3:.3f} ms  "
-        f"phases {dict(zip(names, np.round(phase, 4)))}  tiers {stats}")
+    log(f"step {ms_step:.3f} ms  wall/step {wall_step * 1e3:.3f} ms  plain "
+        f"{plain_ms:.3f} ms  phases {dict(zip(names, np.round(phase, 4)))}  "
+        f"tiers {stats}")
 
     out = {
         "metric": METRIC,
@@ -308,14 +390,27 @@ def main():
         "alignments_per_s": round(n / (ms_step / 1e3), 1),
         "live_gcups": round(live / (ms_step / 1e3) / 1e9, 1),
         "live_cells": live,
+        "form": {"variant": form.variant, "tile": form.tile,
+                 "chunk": form.chunk},
+        "plain_ms_per_step": round(plain_ms, 4),
+        "speedup_vs_plain": round(plain_ms / ms_step, 3),
         "phase_ms": dict(zip(names, [round(float(x), 4) for x in phase])),
+        "tiers": stats,
         "tuned": tuned,
         "roofline": {"bound": "alu", "kernel": names[dom],
                      "achieved": round(achieved, 3),
                      "peak": round(INT32_PEAK_TOPS, 1), "unit": "TOP/s",
                      "frac": round(achieved / INT32_PEAK_TOPS, 4),
                      "traffic": measured_traffic(args.workload)},
+        "unmeasured": UNMEASURED,
     }
+    others = [w for w in args.others.split(",") if w and w != args.workload]
+    if others:
+        out["other_workloads"] = {}
+        for w in others:
+            log(f"other workload {w}")
+            out["other_workloads"][w] = other_workload(
+                xdrop, ctx, w, 20 if w == "dna-1k" else 5, stream)
     ctx.close()
     if args.serve_requests > 0:
         log("serving run")

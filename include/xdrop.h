@@ -180,11 +180,18 @@ int xdrop_extend_batch_noalloc(xdrop_ctx *ctx, const uint8_t *d_seqs,
                                const xdrop_options *opts,
                                xdrop_result *d_results, void *stream);
 
-/* Autotune the launch parameters on a sample batch (same arguments as
- * xdrop_extend_batch; d_results is scratch) by timing every candidate
- * variant / tile / chunk on `stream`; the best is stored in the context for
- * batches of this alphabet and, if cache_path is not NULL, appended to that
- * JSON-lines file.  *best_out (optional) receives the chosen options. */
+/* Autotune the launch parameters (paper Sec. 4.2: batching extensions of
+ * uneven lengths; here the launch form, the starting tile and the queue
+ * chunk) on a sample batch: same arguments as xdrop_extend_batch, d_results
+ * is scratch.  Every candidate variant / tile / chunk is timed on `stream`
+ * (median of three runs after a warm run); the fastest is stored in the
+ * context for batches of the same key -- alphabet, X class (X < 24, < 100,
+ * >= 100: a stand-in for the band width) and batch size class (seeds
+ * < 2,048, < 32,768, < 524,288, more) -- and, if cache_path is not NULL,
+ * appended to that JSON-lines file with the device architecture, the
+ * sample's mean extension length and the time of the plain form.
+ * *best_out (optional) receives the chosen options.  Synchronises `stream`.
+ * Results of later batches do not depend on the choice (bit-exact). */
 int xdrop_autotune(xdrop_ctx *ctx, const uint8_t *d_seqs,
                    const int64_t *d_offsets, int32_t n_seqs,
                    const xdrop_seed *d_seeds, int32_t n_seeds,
@@ -192,8 +199,19 @@ int xdrop_autotune(xdrop_ctx *ctx, const uint8_t *d_seqs,
                    void *stream, const char *cache_path,
                    xdrop_options *best_out);
 
-/* Load tuned options from a JSON-lines cache written by xdrop_autotune. */
+/* Load tuned options from a JSON-lines cache written by xdrop_autotune:
+ * entries whose "arch" is this device's architecture and that hold every
+ * key (alphabet, x_class, size_class, variant, tile, chunk, waves_per_cu);
+ * a later entry of the same key replaces an earlier one.  XDROP_E_INVALID
+ * if the file cannot be read or holds no usable entry. */
 int xdrop_load_tuning(xdrop_ctx *ctx, const char *cache_path);
+
+/* The options a batch of n_seeds seeds with this scoring would run with
+ * (caller's options over the tuned entry of its key over the defaults, with
+ * the automatic form and chunk resolved); nothing is launched. */
+int xdrop_resolve_options(xdrop_ctx *ctx, const xdrop_scoring *scoring,
+                          int32_t n_seeds, const xdrop_options *opts,
+                          xdrop_options *out);
 
 /* Capture the launch sequence of one batch shape into a HIP graph and replay
  * it: identical to xdrop_extend_batch, but the launches are recorded once per

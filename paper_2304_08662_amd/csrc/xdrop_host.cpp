@@ -33,6 +33,23 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
 };
 
+// Tuned launch options apply to batches of one alphabet, X class and batch
+// size class: the launch form is chosen on the host before any device data
+// is read, and these are what the host knows.  X stands in for the band
+// width (the tile), the batch size for how many waves the queue feeds (the
+// form and the chunk).
+struct TuneKey {
+  int alphabet, x_class, size_class;
+  bool operator==(const TuneKey& o) const {
+    return alphabet == o.alphabet && x_class == o.x_class &&
+           size_class == o.size_class;
+  }
+};
+struct TunedEntry {
+  TuneKey key;
+  xdrop_options opts;
+};
+
 struct xdrop_ctx {
   int device = 0;
   int num_cu = 0;
@@ -48,8 +65,8 @@ struct xdrop_ctx {
   int pair_blocks_per_cu[2] = {0, 0};
   int block_blocks_per_cu[2] = {0, 0};
   int blocks_per_cu[2] = {0, 0};  // [alphabet]
-  bool have_tuned[2] = {false, false};
-  xdrop_options tuned[2];
+  std::string arch;  // gfx name of the device (tuning cache key)
+  std::vector<TunedEntry> tuned;  // xdrop_autotune / xdrop_load_tuning
   std::vector<GraphEntry> graphs;
   // phase timing (xdrop_ctx_set_timing): one set of events around the
   // launch phases per batch, summed by xdrop_last_timing
@@ -160,11 +177,23 @@ int check_options(const xdrop_options* o) {
   return XDROP_OK;
 }
 
+int x_class(int32_t X) { return X < 24 ? 0 : X < 100 ? 1 : 2; }
+int size_class(int32_t n_seeds) {
+  return n_seeds < 2048 ? 0 : n_seeds < 32768 ? 1 : n_seeds < 524288 ? 2 : 3;
+}
+TuneKey tune_key(const xdrop_scoring* sc, int32_t n_seeds) {
+  return TuneKey{sc->alphabet == XDROP_BYTE ? 1 : 0, x_class(sc->X),
+                 size_class(n_seeds)};
+}
+
+// Options of a batch: the caller's, over the tuned entry of the batch's key
+// (if any), over the defaults.
 xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
-                      const xdrop_options* o) {
+                      const xdrop_options* o, int32_t n_seeds) {
   xdrop_options r{};
-  const int a = sc->alphabet == XDROP_BYTE ? 1 : 0;
-  if (c->have_tuned[a]) r = c->tuned[a];
+  const TuneKey k = tune_key(sc, n_seeds);
+  for (const auto& t : c->tuned)
+    if (t.key == k) r = t.opts;
   if (o) {
     if (o->variant) r.variant = o->variant;
     if (o->tile) r.tile = o->tile;
@@ -173,14 +202,30 @@ xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
     r.order = o->order;
     if (o->waves_per_cu) r.waves_per_cu = o->waves_per_cu;
   }
-  // (AUTO stays 0 here: enqueue picks PLAIN or WAVE from the batch size)
   // the pair kernel keeps no per-antidiagonal band width: a band cap runs on
   // the wave kernel
   if (r.variant == XDROP_VARIANT_PAIR && r.band_cap > 0)
     r.variant = XDROP_VARIANT_WAVE;
   if (!r.tile) r.tile = 1;
-  // chunk 0 = automatic, sized per batch in enqueue
   return r;
+}
+
+// The automatic choices that depend on the batch size: the queue chunk (one
+// extension per claim while the batch fills the persistent grid at most a
+// few times over, where longest-first balance matters most; up to 8 per
+// claim for large batches, fewer contended atomics on the queue head) and
+// the form (a batch within one wave of the persistent grid starts every
+// extension at once: the plain form, one launched wave per extension, then
+// does the same work without the queue and the longest-first order).
+void finalize(const xdrop_ctx* c, int alphabet, int32_t n_items,
+              xdrop_options& o) {
+  const int64_t waves = (int64_t)c->num_cu * c->blocks_per_cu[alphabet] * WPB;
+  if (!o.chunk)
+    o.chunk = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(8, n_items / (waves * 8)));
+  if (o.variant == XDROP_VARIANT_AUTO)
+    o.variant = (o.waves_per_cu == 0 && (int64_t)n_items <= waves)
+                    ? XDROP_VARIANT_PLAIN : XDROP_VARIANT_WAVE;
 }
 
 void drop_graphs(xdrop_ctx* c);
@@ -240,7 +285,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   if (n_seeds == 0) return XDROP_OK;
   if (!d_seqs || !d_offsets || !d_seeds || !d_results || n_seqs == 0)
     return XDROP_E_INVALID;
-  xdrop_options o = resolve(c, sc, opts);
+  xdrop_options o = resolve(c, sc, opts, n_seeds);
   const int32_t n_items = 2 * n_seeds;
   Layout L = layout(n_items, n_seqs);
   Workspace W;
@@ -268,30 +313,10 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   P.n_seeds = n_seeds;
   P.n_items = n_items;
   P.tile = o.tile;
-  {
-    // automatic chunk: one extension per claim while the batch fills the
-    // persistent grid at most a few times over (longest-first balance
-    // matters most there), up to 8 per claim for large batches (fewer
-    // contended atomics on the queue head)
-    const int a0 = P.alphabet;
-    if (!c->blocks_per_cu[a0]) c->blocks_per_cu[a0] = wave_blocks_per_cu(a0);
-    const int64_t waves = (int64_t)c->num_cu * c->blocks_per_cu[a0] * WPB;
-    if (!o.chunk)
-      o.chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(8, n_items / (waves * 8)));
-  }
+  finalize(c, P.alphabet, n_items, o);
   P.chunk = o.chunk;
   P.band_cap = o.band_cap;
   P.gen_slots = W.gen_slots;
-  if (o.variant == XDROP_VARIANT_AUTO) {
-    // a batch within one wave of the persistent grid starts every extension
-    // at once: the plain form (one launched wave per extension) then does
-    // the same work without the queue and the longest-first order, which
-    // it measured faster on such batches; larger batches take the queue
-    const int a0 = P.alphabet;
-    const int64_t waves = (int64_t)c->num_cu * c->blocks_per_cu[a0] * WPB;
-    o.variant = (o.waves_per_cu == 0 && (int64_t)n_items <= waves)
-                    ? XDROP_VARIANT_PLAIN : XDROP_VARIANT_WAVE;
-  }
   const bool plain = o.variant == XDROP_VARIANT_PLAIN;
   P.flags = plain ? F_PLAIN : 0;
 
@@ -322,7 +347,6 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     P.flags |= F_ORDERED;
   }
   const int a = P.alphabet;
-  if (!c->blocks_per_cu[a]) c->blocks_per_cu[a] = wave_blocks_per_cu(a);
   auto persistent_grid = [&]() {
     int bpc = c->blocks_per_cu[a];
     if (o.waves_per_cu > 0)
@@ -339,7 +363,6 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   } else if (o.variant == XDROP_VARIANT_PAIR) {
     // two extensions per wave; bands wider than 32 cells are handed on to
     // the wave kernel
-    if (!c->pair_blocks_per_cu[a]) c->pair_blocks_per_cu[a] = pair_blocks_per_cu(a);
     const int pairs = (n_items + 1) / 2;
     const int pgrid = std::min(c->num_cu * c->pair_blocks_per_cu[a],
                                (pairs + WPB - 1) / WPB);
@@ -363,7 +386,6 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   // extensions whose band outgrew one wave's window: the block tier, and
   // beyond 2,048 cells the device-memory tier (both leave at once when
   // nothing was handed to them)
-  if (!c->block_blocks_per_cu[a]) c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
   HIP_OK(launch_block(P, std::min(c->num_cu * c->block_blocks_per_cu[a],
                                   n_items), st));
   HIP_OK(launch_general(P, W.gen_slots, st));
@@ -417,6 +439,8 @@ int xdrop_ctx_create(int device, xdrop_ctx** out) {
     return XDROP_E_DEVICE;
   }
   c->num_cu = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  c->arch = c->arch.substr(0, c->arch.find(':'));
   // occupancy of every kernel form, queried once here (the launch paths then
   // make no runtime queries, under graph capture or otherwise)
   for (int a = 0; a < 2; ++a) {
@@ -582,7 +606,7 @@ extern "C" int xdrop_extend_batch_graph(
   if (!d_seqs || !d_offsets || !d_seeds || !d_results || n_seqs == 0)
     return XDROP_E_INVALID;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
-  const xdrop_options o = resolve(c, sc, opts);
+  const xdrop_options o = resolve(c, sc, opts, n_seeds);
   for (auto& g : c->graphs) {
     if (g.seqs == d_seqs && g.offsets == d_offsets && g.seeds == d_seeds &&
         g.results == d_results && g.n_seqs == n_seqs &&
@@ -596,13 +620,6 @@ extern "C" int xdrop_extend_batch_graph(
   Layout L = layout(2 * n_seeds, n_seqs);
   rc = ensure_workspace(c, L.total, st);  // (drops the graphs if it moves)
   if (rc != XDROP_OK) return rc;
-  for (int a = 0; a < 2; ++a) {
-    if (!c->blocks_per_cu[a]) c->blocks_per_cu[a] = wave_blocks_per_cu(a);
-    if (!c->block_blocks_per_cu[a])
-      c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
-    if (!c->pair_blocks_per_cu[a])
-      c->pair_blocks_per_cu[a] = pair_blocks_per_cu(a);
-  }
   GraphEntry g;
   g.seqs = d_seqs; g.offsets = d_offsets; g.seeds = d_seeds;
   g.results = d_results; g.n_seqs = n_seqs; g.n_seeds = n_seeds;
@@ -643,6 +660,41 @@ extern "C" int xdrop_extend_batch_graph(
 }
 
 // ------------------------------------------------------------------ tuning
+namespace {
+
+// Mean extension length m + n of a batch (host copies of its offsets and
+// seeds; recorded with the tuned choice).
+int mean_extension_length(const int64_t* d_offsets, int32_t n_seqs,
+                          const xdrop_seed* d_seeds, int32_t n_seeds,
+                          double* out) {
+  std::vector<int64_t> off((size_t)n_seqs + 1);
+  std::vector<xdrop_seed> sd((size_t)n_seeds);
+  if (hipMemcpy(off.data(), d_offsets, off.size() * sizeof(int64_t),
+                hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(sd.data(), d_seeds, sd.size() * sizeof(xdrop_seed),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return XDROP_E_DEVICE;
+  double sum = 0;
+  for (const auto& z : sd) {
+    if (z.q < 0 || z.q >= n_seqs || z.t < 0 || z.t >= n_seqs) continue;
+    sum += (double)(off[z.q + 1] - off[z.q]) +
+           (double)(off[z.t + 1] - off[z.t]) - 2.0 * z.k;
+  }
+  *out = sum / (2.0 * std::max(n_seeds, 1));
+  return XDROP_OK;
+}
+
+void set_tuned(xdrop_ctx* c, const TuneKey& k, const xdrop_options& o) {
+  for (auto& t : c->tuned)
+    if (t.key == k) {
+      t.opts = o;
+      return;
+    }
+  c->tuned.push_back(TunedEntry{k, o});
+}
+
+}  // namespace
+
 extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
                               const int64_t* d_offsets, int32_t n_seqs,
                               const xdrop_seed* d_seeds, int32_t n_seeds,
@@ -652,13 +704,18 @@ extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
                               xdrop_options* best_out) {
   if (!c || !sc) return XDROP_E_INVALID;
   if (c->sticky != XDROP_OK) return c->sticky;
-  if (n_seeds <= 0) return XDROP_E_INVALID;
+  if (n_seeds <= 0 || n_seqs <= 0 || !d_offsets || !d_seeds)
+    return XDROP_E_INVALID;
+  Params tmp;
+  int rc = fill_scoring(sc, tmp);
+  if (rc != XDROP_OK) return rc;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
   hipStream_t st = (hipStream_t)stream;
-  const int a = sc->alphabet == XDROP_BYTE ? 1 : 0;
+  const TuneKey key = tune_key(sc, n_seeds);
   // candidates: the pair form (tile and chunk of the wave kernel that takes
   // the extensions it hands on), the persistent wave form (tile x chunk),
-  // the plain form (tile), the workgroup form
+  // the plain form (tile), the workgroup form; every field is set, so no
+  // tuned entry applies while they are timed
   std::vector<xdrop_options> cand;
   const int tiles[] = {1, 2, 4, 8};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
@@ -684,14 +741,14 @@ extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
     o.variant = XDROP_VARIANT_WORKGROUP; o.tile = 1; o.chunk = 1;
     cand.push_back(o);
   }
+  double mean_len = 0;
+  rc = mean_extension_length(d_offsets, n_seqs, d_seeds, n_seeds, &mean_len);
+  if (rc != XDROP_OK) return fail(c, hipErrorUnknown);
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
-  const bool saved = c->have_tuned[a];
-  c->have_tuned[a] = false;  // time each candidate as given
-  float best_ms = 1e30f;
+  float best_ms = 1e30f, plain_ms = 0.f;
   xdrop_options best{};
-  int rc = XDROP_OK;
   for (const auto& o : cand) {
     // one warm run, then the median of three timed runs (one if slow)
     rc = enqueue(c, d_seqs, d_offsets, n_seqs, d_seeds, n_seeds, sc, &o,
@@ -712,26 +769,26 @@ extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
     if (rc != XDROP_OK) break;
     std::sort(t, t + reps);
     const float ms = t[reps / 2];
+    if (o.variant == XDROP_VARIANT_PLAIN && o.tile == 1) plain_ms = ms;
     if (ms < best_ms) { best_ms = ms; best = o; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (rc != XDROP_OK) {
-    c->have_tuned[a] = saved;
-    return rc;
-  }
-  c->tuned[a] = best;
-  c->have_tuned[a] = true;
+  if (rc != XDROP_OK) return rc;
+  set_tuned(c, key, best);
   if (best_out) *best_out = best;
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (!f) return XDROP_E_INVALID;
     std::fprintf(f,
-                 "{\"arch\": \"gfx950\", \"alphabet\": %d, \"X\": %d, "
-                 "\"n_seeds\": %d, \"variant\": %d, \"tile\": %d, "
-                 "\"chunk\": %d, \"waves_per_cu\": %d, \"ms\": %.4f}\n",
-                 a, sc->X, n_seeds, best.variant, best.tile, best.chunk,
-                 best.waves_per_cu, best_ms);
+                 "{\"arch\": \"%s\", \"alphabet\": %d, \"x_class\": %d, "
+                 "\"size_class\": %d, \"variant\": %d, \"tile\": %d, "
+                 "\"chunk\": %d, \"waves_per_cu\": %d, \"X\": %d, "
+                 "\"n_seeds\": %d, \"mean_extension_length\": %.1f, "
+                 "\"ms\": %.4f, \"plain_ms\": %.4f}\n",
+                 c->arch.c_str(), key.alphabet, key.x_class, key.size_class,
+                 best.variant, best.tile, best.chunk, best.waves_per_cu,
+                 sc->X, n_seeds, mean_len, best_ms, plain_ms);
     std::fclose(f);
   }
   return XDROP_OK;
@@ -744,6 +801,16 @@ bool json_int(const std::string& line, const char* key, int* out) {
   if (p == std::string::npos) return false;
   return std::sscanf(line.c_str() + p + k.size(), " %d", out) == 1;
 }
+bool json_str(const std::string& line, const char* key, std::string* out) {
+  const std::string k = std::string("\"") + key + "\": \"";
+  size_t p = line.find(k);
+  if (p == std::string::npos) return false;
+  p += k.size();
+  const size_t e = line.find('"', p);
+  if (e == std::string::npos) return false;
+  *out = line.substr(p, e - p);
+  return true;
+}
 }  // namespace
 
 extern "C" int xdrop_load_tuning(xdrop_ctx* c, const char* cache_path) {
@@ -753,21 +820,44 @@ extern "C" int xdrop_load_tuning(xdrop_ctx* c, const char* cache_path) {
   char buf[1024];
   int loaded = 0;
   while (std::fgets(buf, sizeof(buf), f)) {
-    std::string line(buf);
-    if (line.find("\"gfx950\"") == std::string::npos) continue;
-    int a, v, t, ch, w = 0;
-    if (!json_int(line, "alphabet", &a) || !json_int(line, "variant", &v) ||
-        !json_int(line, "tile", &t) || !json_int(line, "chunk", &ch))
-      continue;
-    json_int(line, "waves_per_cu", &w);
-    if (a < 0 || a > 1) continue;
+    const std::string line(buf);
+    // every key of an entry must be present; entries of another device
+    // architecture are skipped
+    std::string arch;
+    TuneKey k{};
     xdrop_options o{};
-    o.variant = v; o.tile = t; o.chunk = ch; o.waves_per_cu = w;
-    if (check_options(&o) != XDROP_OK) continue;
-    c->tuned[a] = o;
-    c->have_tuned[a] = true;
+    if (!json_str(line, "arch", &arch) || arch != c->arch ||
+        !json_int(line, "alphabet", &k.alphabet) ||
+        !json_int(line, "x_class", &k.x_class) ||
+        !json_int(line, "size_class", &k.size_class) ||
+        !json_int(line, "variant", &o.variant) ||
+        !json_int(line, "tile", &o.tile) ||
+        !json_int(line, "chunk", &o.chunk) ||
+        !json_int(line, "waves_per_cu", &o.waves_per_cu))
+      continue;
+    if (k.alphabet < 0 || k.alphabet > 1 || k.x_class < 0 || k.x_class > 2 ||
+        k.size_class < 0 || k.size_class > 3 || o.variant == 0 ||
+        check_options(&o) != XDROP_OK)
+      continue;
+    set_tuned(c, k, o);  // a later line of the same key replaces an earlier
     ++loaded;
   }
   std::fclose(f);
   return loaded ? XDROP_OK : XDROP_E_INVALID;
+}
+
+extern "C" int xdrop_resolve_options(xdrop_ctx* c, const xdrop_scoring* sc,
+                                     int32_t n_seeds,
+                                     const xdrop_options* opts,
+                                     xdrop_options* out) {
+  if (!c || !sc || !out || n_seeds < 0) return XDROP_E_INVALID;
+  Params tmp;
+  int rc = fill_scoring(sc, tmp);
+  if (rc != XDROP_OK) return rc;
+  rc = check_options(opts);
+  if (rc != XDROP_OK) return rc;
+  xdrop_options o = resolve(c, sc, opts, n_seeds);
+  finalize(c, sc->alphabet == XDROP_BYTE ? 1 : 0, 2 * n_seeds, o);
+  *out = o;
+  return XDROP_OK;
 }

@@ -93,7 +93,8 @@ class ServerOpts(ctypes.Structure):
 EXPORTS = ["xdrop_ctx_create", "xdrop_ctx_destroy", "xdrop_extend_batch",
            "xdrop_extend_batch_noalloc",
            "xdrop_ctx_set_timing", "xdrop_last_timing",
-           "xdrop_autotune", "xdrop_load_tuning", "xdrop_extend_batch_graph",
+           "xdrop_autotune", "xdrop_load_tuning", "xdrop_resolve_options",
+           "xdrop_extend_batch_graph",
            "xdrop_last_stats", "xdrop_server_create", "xdrop_server_submit",
            "xdrop_server_poll", "xdrop_server_wait", "xdrop_server_destroy",
            "xdrop_strerror"]
@@ -124,6 +125,9 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(Scoring), vp, vp,
                                    ctypes.c_char_p, ctypes.POINTER(Options)]
     lib.xdrop_load_tuning.argtypes = [vp, ctypes.c_char_p]
+    lib.xdrop_resolve_options.argtypes = [vp, ctypes.POINTER(Scoring), i32,
+                                          ctypes.POINTER(Options),
+                                          ctypes.POINTER(Options)]
     lib.xdrop_last_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
     lib.xdrop_ctx_set_timing.argtypes = [vp, i32]
     lib.xdrop_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32,
@@ -252,6 +256,17 @@ class Context:
     def load_tuning(self, cache_path: str):
         _check(self.lib.xdrop_load_tuning(self.handle, cache_path.encode()),
                "xdrop_load_tuning")
+
+    def resolve_options(self, scoring: ScoringSpec, n_seeds: int,
+                        opts: Options | None = None) -> Options:
+        """The options a batch of n_seeds seeds would run with."""
+        sc = scoring.c()
+        out = Options()
+        _check(self.lib.xdrop_resolve_options(
+            self.handle, ctypes.byref(sc), n_seeds,
+            ctypes.byref(opts) if opts is not None else None,
+            ctypes.byref(out)), "xdrop_resolve_options")
+        return out
 
     def set_timing(self, on: bool = True):
         _check(self.lib.xdrop_ctx_set_timing(self.handle, int(on)),
