@@ -133,8 +133,21 @@ typedef struct {
 
 typedef struct xdrop_ctx xdrop_ctx;
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
-int xdrop_ctx_create(int device, xdrop_ctx **out);
+/* Context options (host struct; NULL = defaults). */
+typedef struct {
+    int32_t device_tier_slots; /* extensions with bands wider than 2,048
+                                  cells that run at once on the
+                                  device-memory tier (each holds 768 KiB of
+                                  rings); 0 = 32 */
+    int32_t reserved[7];
+} xdrop_ctx_opts;
+
+/* Create a context on HIP device `device` (the device is made current).
+ * *out receives the handle.  A context owns the device workspace of its
+ * batches, which every batch reuses: batches on one context must run one
+ * after another -- enqueue them on one stream, or order the streams (an
+ * event wait, or a synchronisation) between batches on different streams. */
+int xdrop_ctx_create(int device, const xdrop_ctx_opts *opts, xdrop_ctx **out);
 int xdrop_ctx_destroy(xdrop_ctx *ctx);
 
 /* Extend every seed of a batch.

@@ -179,7 +179,7 @@ def extend_matrix(a, b, scoring: Scoring):
 
 
 def band_widths(a, b, scoring: Scoring, finite: bool = False):
-    """Working band hi_d - lo_d + 1 per antidiagonal (Sec. 5.4 study); with
+    """Working band hi_d - lo_d + 1 per antidiagonal (Sec. 6.1 study); with
     finite=True also the finite range (L_d, U_d; -1 when dead) per d."""
     lib = _load()
     a = _u8(a)

@@ -8,7 +8,8 @@
  *
  * What is computed (paper: Sec. 2.2 recurrence and X-Drop rule, Sec. 3 and
  * Algorithm 1 for the antidiagonal order, the threshold timing and the
- * termination test, Sec. 4.1.1 for the seed / left-right split):
+ * termination test, Sec. 4.1.1 and 4.1.2 for the seed and the left / right
+ * split):
  *
  *   Cells (x, y), 0 <= x <= m, 0 <= y <= n: x symbols of a (the query side,
  *   the paper's H) and y symbols of b (the target side, the paper's V) are
@@ -239,7 +240,7 @@ static xo_cell xo_get(const xo_diag *D, const xo_cell *store, int64_t d,
 }
 
 /* widths (optional, m+n+1 entries): hi_d - lo_d + 1 per antidiagonal, 0 when
- * empty -- the working band of Sec. 5.4.  finite (optional, 2*(m+n+1)
+ * empty -- the working band of Sec. 6.1.  finite (optional, 2*(m+n+1)
  * entries): L_d, U_d per antidiagonal, -1, -1 when it holds no finite cell. */
 int xo_extend_span(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
                    const xo_scoring *sc, xo_ext *out, int32_t *widths,

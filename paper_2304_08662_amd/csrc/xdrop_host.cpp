@@ -420,15 +420,19 @@ const char* xdrop_strerror(int s) {
   }
 }
 
-int xdrop_ctx_create(int device, xdrop_ctx** out) {
+int xdrop_ctx_create(int device, const xdrop_ctx_opts* opts,
+                     xdrop_ctx** out) {
   if (!out) return XDROP_E_INVALID;
   *out = nullptr;
+  if (opts && (opts->device_tier_slots < 0 || opts->device_tier_slots > 1024))
+    return XDROP_E_INVALID;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
     return XDROP_E_INVALID;
   xdrop_ctx* c = new (std::nothrow) xdrop_ctx();
   if (!c) return XDROP_E_NOMEM;
   c->device = device;
+  if (opts && opts->device_tier_slots) c->gen_slots = opts->device_tier_slots;
   if (hipSetDevice(device) != hipSuccess) {
     delete c;
     return XDROP_E_DEVICE;

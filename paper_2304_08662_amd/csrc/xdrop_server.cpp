@@ -343,7 +343,7 @@ int xdrop_server_create(int device, size_t hbm_budget_bytes,
                   hipSuccess &&
               hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) ==
                   hipSuccess &&
-              xdrop_ctx_create(device, &sl.ctx) == XDROP_OK &&
+              xdrop_ctx_create(device, nullptr, &sl.ctx) == XDROP_OK &&
               hipMalloc(&sl.d_offsets, (size_t)(s->max_batch_seqs + 1) * 8) ==
                   hipSuccess &&
               hipMalloc(&sl.d_seeds, (size_t)s->max_batch_seeds *

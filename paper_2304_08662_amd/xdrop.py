@@ -74,6 +74,11 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 2)]
 
 
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("device_tier_slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("seqs", ctypes.c_void_p),
                 ("offsets", ctypes.c_void_p),
@@ -114,7 +119,8 @@ def load_library(path: str = LIB_PATH):
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     lib.xdrop_strerror.restype = ctypes.c_char_p
     lib.xdrop_strerror.argtypes = [ctypes.c_int]
-    lib.xdrop_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.xdrop_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(CtxOpts),
+                                     ctypes.POINTER(vp)]
     lib.xdrop_ctx_destroy.argtypes = [vp]
     batch_args = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(Scoring),
                   ctypes.POINTER(Options), vp, vp]
@@ -202,10 +208,11 @@ def _ptr(t):
 class Context:
     """A library context on one device (owns the device workspace)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, device_tier_slots: int = 0):
         self.lib = load_library()
         h = ctypes.c_void_p()
-        _check(self.lib.xdrop_ctx_create(device, ctypes.byref(h)),
+        o = CtxOpts(device_tier_slots)
+        _check(self.lib.xdrop_ctx_create(device, ctypes.byref(o), ctypes.byref(h)),
                "xdrop_ctx_create")
         self.handle = h
         self.device = device

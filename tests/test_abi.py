@@ -57,7 +57,7 @@ def test_null_handles_are_rejected(lib):
 def test_ctx_create_rejects_missing_device(lib):
     from paper_2304_08662_amd import xdrop
     h = ctypes.c_void_p()
-    rc = lib.xdrop_ctx_create(4096, ctypes.byref(h))
+    rc = lib.xdrop_ctx_create(4096, None, ctypes.byref(h))
     assert rc == xdrop.E_INVALID and not h.value
 
 

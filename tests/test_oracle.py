@@ -307,7 +307,7 @@ def test_appending_after_termination_changes_nothing(seed):
 
 
 def test_band_grows_with_x():
-    # Sec. 5.4: a larger X keeps a wider working band
+    # Sec. 6.1: a larger X keeps a wider working band
     rng = np.random.default_rng(11)
     a = rng.integers(0, 4, 600).astype(np.uint8)
     b = a.copy()

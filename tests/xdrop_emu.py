@@ -32,7 +32,7 @@ class EmuLib:
                 build()
         lib = ctypes.CDLL(path)
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
-        lib.xdrop_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        lib.xdrop_ctx_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
         lib.xdrop_ctx_destroy.argtypes = [vp]
         args = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(xdrop.Scoring),
                 ctypes.POINTER(xdrop.Options), vp, vp]
@@ -46,7 +46,7 @@ class EmuLib:
             getattr(lib, f).restype = ctypes.c_int
         self.lib = lib
         h = ctypes.c_void_p()
-        rc = lib.xdrop_ctx_create(0, ctypes.byref(h))
+        rc = lib.xdrop_ctx_create(0, None, ctypes.byref(h))
         assert rc == 0, rc
         self.ctx = h
 
