@@ -124,29 +124,63 @@ def cpu_baseline(batch, scheme, target_s: float, gpu_cells_per_seed):
 
 def serving_run(xdrop, n_requests: int, rates=(0.8,), budget=64 << 30):
     """Poisson request stream (1-4096 pairs, log-uniform; DNA 1k-generator or
-    protein-generator pairs drawn from pools): saturation throughput from a
-    closed burst, then p50/p99 latency at the given fractions of it."""
+    protein-generator pairs drawn from two pools), served twice: with every
+    request carrying its own copy of its sequences, and with the pools
+    resident once as sequence sets that requests seed against.  Saturation
+    throughput from a closed burst, host-to-device bytes of each, then
+    p50/p99 latency of the resident-set form at the given fractions of its
+    saturation."""
     from paper_2304_08662_amd import inputs
-    srv = xdrop.Server(0, budget_bytes=budget)
     rng = inputs.rng_for(5)
-    reqs = [(b, s) for _, b, s in
-            inputs.request_stream_pooled(rng, n_requests, 0.0)]
-    packed = [(b.packed() if b.alphabet == 4 else b.codes) for b, _ in reqs]
-    scs = [scoring_for(xdrop, s) for _, s in reqs]
-    # saturation: everything at once
-    t0 = time.perf_counter()
-    tk = [srv.submit(p, b.offsets, b.seeds, sc)
-          for p, (b, _), sc in zip(packed, reqs, scs)]
-    for t, (b, _) in zip(tk, reqs):
-        srv.wait(t, len(b.seeds))
-    sat_s = time.perf_counter() - t0
-    n_aln = sum(len(b.seeds) for b, _ in reqs)
-    cells = sum(b.gcups_cells() for b, _ in reqs)
-    sat_req_per_s = n_requests / sat_s
-    out = {"requests": n_requests, "alignments": n_aln,
-           "saturation_req_per_s": round(sat_req_per_s, 1),
-           "saturation_aln_per_s": round(n_aln / sat_s, 1),
-           "saturation_gcups": round(cells / sat_s / 1e9, 1), "rates": []}
+    pools = inputs.request_pools(rng, 8192)
+    refs = list(inputs.request_refs(rng, n_requests, 0.0, 8192))
+    n_aln = sum(len(idx) for _, _, idx in refs)
+    cells = 0
+    for _, w, idx in refs:
+        pool = pools[w][0]
+        L = pool.lengths()
+        cells += int(np.sum(L[pool.seeds["q"][idx]].astype(np.int64) *
+                            L[pool.seeds["t"][idx]]))
+    scs = [scoring_for(xdrop, sch) for _, sch in pools]
+
+    def burst(srv, submit):
+        t0 = time.perf_counter()
+        tk = [submit(i) for i in range(n_requests)]
+        for i, t in enumerate(tk):
+            srv.wait(t, len(refs[i][2]))
+        return time.perf_counter() - t0
+
+    out = {"requests": n_requests, "alignments": n_aln}
+    # every request with its own sequences
+    own = [pools[w][0].subset(idx) for _, w, idx in refs]
+    packed = [(b.packed() if b.alphabet == 4 else b.codes) for b in own]
+    srv = xdrop.Server(0, budget_bytes=budget)
+    sat = burst(srv, lambda i: srv.submit(packed[i], own[i].offsets,
+                                          own[i].seeds, scs[refs[i][1]]))
+    out["own_copies"] = {"saturation_aln_per_s": round(n_aln / sat, 1),
+                         "saturation_gcups": round(cells / sat / 1e9, 1),
+                         "h2d_bytes": srv.stats()["h2d_bytes"]}
+    srv.close()
+    del own, packed
+    # the pools resident once; requests seed against them
+    srv = xdrop.Server(0, budget_bytes=budget)
+    sids = [srv.put_sequences(p.packed() if p.alphabet == 4 else p.codes,
+                              p.offsets, xdrop.DNA2 if p.alphabet == 4
+                              else xdrop.BYTE) for p, _ in pools]
+    seeds = [pools[w][0].seeds[idx] for _, w, idx in refs]
+
+    def submit_ref(i):
+        w = refs[i][1]
+        return srv.submit(None, None, seeds[i], scs[w], seq_set=sids[w])
+
+    sat = burst(srv, submit_ref)
+    sat_req_per_s = n_requests / sat
+    st = srv.stats()
+    res = {"saturation_req_per_s": round(sat_req_per_s, 1),
+           "saturation_aln_per_s": round(n_aln / sat, 1),
+           "saturation_gcups": round(cells / sat / 1e9, 1),
+           "h2d_bytes": st["h2d_bytes"], "reused_bytes": st["reused_bytes"],
+           "rates": []}
     for frac in rates:
         rate = frac * sat_req_per_s
         gaps = np.random.default_rng(11).exponential(1.0 / rate, n_requests)
@@ -158,12 +192,11 @@ def serving_run(xdrop, n_requests: int, rates=(0.8,), budget=64 << 30):
         while i < n_requests or pending:
             now = time.perf_counter() - start
             while i < n_requests and arrive[i] <= now:
-                b, _ = reqs[i]
-                pending[srv.submit(packed[i], b.offsets, b.seeds, scs[i])] = i
+                pending[submit_ref(i)] = i
                 i += 1
             done = []
             for t, j in pending.items():
-                if srv.poll(t, len(reqs[j][0].seeds)) is not None:
+                if srv.poll(t, len(refs[j][2])) is not None:
                     lat[j] = time.perf_counter() - start - arrive[j]
                     done.append(t)
             for t in done:
@@ -171,14 +204,19 @@ def serving_run(xdrop, n_requests: int, rates=(0.8,), budget=64 << 30):
             if not done:
                 time.sleep(20e-6)
         wall = time.perf_counter() - start
-        out["rates"].append({
+        res["rates"].append({
             "fraction_of_saturation": frac,
             "req_per_s": round(rate, 1),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
             "aln_per_s": round(n_aln / wall, 1),
             "gcups": round(cells / wall / 1e9, 1)})
+    st = srv.stats()
+    res["max_batches_in_flight"] = st["max_batches_in_flight"]
+    res["admitted_while_busy"] = st["admitted_while_busy"]
     srv.close()
+    out["resident_sets"] = res
+    out["h2d_bytes_saved"] = out["own_copies"]["h2d_bytes"] - res["h2d_bytes"]
     return out
 
 

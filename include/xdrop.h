@@ -266,30 +266,69 @@ int xdrop_last_stats(xdrop_ctx *ctx, int64_t *counts, int32_t n_counts);
 typedef struct xdrop_server xdrop_server;
 
 typedef struct {
-    const uint8_t *seqs;     /* host, packed stream as for xdrop_extend_batch */
-    const int64_t *offsets;  /* host, n_seqs+1 */
+    const uint8_t *seqs;     /* host, packed stream as for xdrop_extend_batch
+                                (ignored when seq_set != 0) */
+    const int64_t *offsets;  /* host, n_seqs+1 (ignored when seq_set != 0) */
     int32_t n_seqs;
-    const xdrop_seed *seeds; /* host */
+    const xdrop_seed *seeds; /* host; q and t index the request's sequences,
+                                or those of the set seq_set */
     int32_t n_seeds;
     xdrop_scoring scoring;
+    uint64_t seq_set;        /* 0: the request's own sequences; else a set
+                                from xdrop_server_put_sequences (same
+                                encoding as scoring.alphabet), shared with
+                                other requests and not copied again */
 } xdrop_request;
 
 typedef struct {
-    int32_t max_inflight;   /* requests resident at once; 0 = 256 */
+    int32_t max_inflight;   /* requests admitted to run at once; 0 = 256 */
     int32_t streams;        /* micro-batches in flight at once; 0 = 4 */
     int32_t arena_mib;      /* sequence arena in MiB; 0 = everything the
                                budget leaves after the per-stream staging and
                                workspace (40 MiB per stream) */
-    int32_t reserved[5];
+    int32_t staging_mib;    /* pinned host staging of sequences not yet on
+                               the device (host memory, outside the budget);
+                               0 = 64 */
+    int32_t reserved[4];
 } xdrop_server_opts;
+
+/* Counters of a server since its creation. */
+typedef struct {
+    int64_t requests_submitted, requests_done;
+    int64_t batches_launched;
+    int64_t batches_in_flight;      /* micro-batches on the device now */
+    int64_t max_batches_in_flight;  /* most at once so far */
+    int64_t admitted_while_busy;    /* requests admitted while a micro-batch
+                                       of other requests was running */
+    int64_t h2d_bytes;              /* sequence bytes copied to the device */
+    int64_t reused_bytes;           /* bytes of the sequences that requests
+                                       seeded against resident sets used
+                                       without copying them */
+    int64_t reserved[8];
+} xdrop_server_counters;
 
 /* hbm_budget_bytes bounds all device memory of the server: the sequence
  * arena plus 40 MiB per stream.  XDROP_E_BUDGET if that does not fit. */
 int xdrop_server_create(int device, size_t hbm_budget_bytes,
                         const xdrop_server_opts *opts, xdrop_server **out);
-/* Copies the request; returns XDROP_E_BUDGET if it can never fit. */
+/* Copies the request (its sequences into pinned staging, from where the
+ * worker moves them to the device asynchronously); returns XDROP_E_BUDGET if
+ * it can never fit, XDROP_E_INVALID for an unknown or released seq_set. */
 int xdrop_server_submit(xdrop_server *srv, const xdrop_request *req,
                         uint64_t *ticket);
+/* Register sequences that many requests will seed against (paper Sec.
+ * 4.1.1 and Sec. 4.3: sequences kept apart from the seed tuples and shared
+ * between comparisons): copied once, resident until released and no
+ * request uses them.  *set_id receives the id for xdrop_request.seq_set.
+ * XDROP_E_BUDGET if the set can never fit the arena or holds more than
+ * 131,071 sequences. */
+int xdrop_server_put_sequences(xdrop_server *srv, const uint8_t *seqs,
+                               const int64_t *offsets, int32_t n_seqs,
+                               int32_t alphabet, uint64_t *set_id);
+/* No new request may use the set; its memory is freed when the requests
+ * that use it are done. */
+int xdrop_server_release_sequences(xdrop_server *srv, uint64_t set_id);
+int xdrop_server_stats(xdrop_server *srv, xdrop_server_counters *out);
 /* XDROP_PENDING or XDROP_OK (then host_out holds n_seeds results and the
  * ticket is released). */
 int xdrop_server_poll(xdrop_server *srv, uint64_t ticket,

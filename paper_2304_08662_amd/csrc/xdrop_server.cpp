@@ -1,15 +1,23 @@
 // Continuous-batching server for X-Drop seed extension.
 //
-// Requests (host sequences, seeds and a scoring scheme) are admitted against
-// a device-memory budget: their packed sequences are copied into a resident
-// device arena as space frees up.  A worker thread groups admitted requests
-// that share a scoring scheme into micro-batches and launches each on one of
-// several streams (one library context per stream), so the work of requests
-// that arrive while others run overlaps on the device.  A micro-batch needs
-// no copy of the sequences: its offsets point into the arena (a gap entry
-// separates requests that are not adjacent), and its seeds are renumbered to
-// those offsets.  Completion is tracked with events; results come back
-// through pinned host memory and each request's arena space is released.
+// Sequences live in a resident device arena, admitted against a memory
+// budget.  They arrive in sets: a request's own sequences form a set that
+// lives as long as the request, and a caller can register a set once
+// (xdrop_server_put_sequences) and let any number of requests seed against
+// it, so a sequence crosses the host link once however many seeds use it
+// (the paper keeps sequences apart from the seed tuples that refer to them
+// and partitions comparisons so that sequences are shared; Sec. 4.1.1,
+// Sec. 4.3).  The caller's thread copies a set into pinned staging memory at
+// submission; the worker thread places it in the arena as space frees up
+// and moves it to the device with an asynchronous copy on a copy stream, so
+// no copy waits on the worker.  Requests whose sequences are resident are
+// grouped by scoring scheme into micro-batches and launched on several
+// streams (one library context per stream): requests that arrive while
+// others run are admitted and their work overlaps on the device.  A
+// micro-batch copies no sequence: its offsets point into the arena (each set
+// once, a gap entry after each), its seeds are renumbered to those offsets.
+// Completion is tracked with events; results come back through pinned host
+// memory, and a set's arena space is released when its last user is done.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,32 +31,20 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "xdrop.h"
 
 namespace {
 
-using Clock = std::chrono::steady_clock;
+constexpr size_t NONE = ~size_t(0);
 
-struct Req {
-  uint64_t ticket = 0;
-  int alphabet = 0;
-  std::vector<uint8_t> seqs;     // packed stream of the request
-  std::vector<int64_t> offsets;  // n_seqs + 1, request-local symbols
-  std::vector<xdrop_seed> seeds;
-  xdrop_scoring sc{};
-  std::vector<int32_t> matrix;
-  size_t arena_off = 0, arena_bytes = 0;  // placement in the arena
-  std::vector<xdrop_result> results;
-  bool done = false;
-  int status = XDROP_OK;
-};
-
-// First-fit allocator over [0, cap) (host bookkeeping of device ranges).
+// First-fit allocator over [0, cap) (host bookkeeping of device or pinned
+// ranges, 256-byte granules).
 class Arena {
  public:
-  explicit Arena(size_t cap) : cap_(cap) { free_[0] = cap; }
+  explicit Arena(size_t cap) : cap_(cap) { if (cap) free_[0] = cap; }
   bool alloc(size_t bytes, size_t* off) {
     bytes = (bytes + 255) & ~size_t(255);
     for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -57,7 +53,6 @@ class Arena {
         size_t rest = it->second - bytes, start = it->first + bytes;
         free_.erase(it);
         if (rest) free_[start] = rest;
-        used_ += bytes;
         return true;
       }
     }
@@ -65,7 +60,6 @@ class Arena {
   }
   void release(size_t off, size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
-    used_ -= bytes;
     auto it = free_.emplace(off, bytes).first;
     auto nx = std::next(it);
     if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -83,8 +77,32 @@ class Arena {
   size_t cap() const { return cap_; }
 
  private:
-  size_t cap_, used_ = 0;
+  size_t cap_;
   std::map<size_t, size_t> free_;
+};
+
+// Sequences of one set: a request's own, or registered for many requests.
+struct SeqSet {
+  uint64_t id = 0;  // 0: a request's own sequences
+  int alphabet = 0;
+  std::vector<int64_t> offsets;  // n_seqs + 1, set-local symbols
+  size_t bytes = 0;              // packed bytes on the device
+  size_t arena_off = 0, arena_bytes = 0;
+  size_t pin_off = NONE;          // host copy in pinned staging, or
+  std::vector<uint8_t> pageable;  // in ordinary memory (staging was full)
+  bool placed = false, resident = false, released = false;
+  int users = 0;  // requests not finished that use the set
+};
+
+struct Req {
+  uint64_t ticket = 0;
+  std::shared_ptr<SeqSet> set;  // the sequences the seeds index
+  std::vector<xdrop_seed> seeds;
+  xdrop_scoring sc{};
+  std::vector<int32_t> matrix;
+  std::vector<xdrop_result> results;
+  bool done = false;
+  int status = XDROP_OK;
 };
 
 struct Slot {  // one stream with its context and staging buffers
@@ -103,55 +121,130 @@ struct Slot {  // one stream with its context and staging buffers
   int32_t n_seeds = 0;
 };
 
+struct CopyRound {  // sets moved to the device by one event
+  hipEvent_t ev = nullptr;
+  std::vector<std::shared_ptr<SeqSet>> sets;
+};
+
 bool same_scoring(const Req& a, const Req& b) {
-  return a.alphabet == b.alphabet && a.sc.alphabet_size == b.sc.alphabet_size &&
+  return a.sc.alphabet == b.sc.alphabet &&
+         a.sc.alphabet_size == b.sc.alphabet_size &&
          a.sc.match == b.sc.match && a.sc.mismatch == b.sc.mismatch &&
          a.sc.gap == b.sc.gap && a.sc.X == b.sc.X && a.matrix == b.matrix;
+}
+
+size_t packed_bytes(int alphabet, int64_t syms) {
+  return alphabet == XDROP_DNA2 ? (size_t)((syms + 15) / 16) * 4
+                                : (size_t)((syms + 3) / 4) * 4;
 }
 
 }  // namespace
 
 struct xdrop_server {
   int device = 0;
-  size_t budget = 0;
   int max_inflight = 256;
   int32_t max_batch_seeds = 1 << 16;
   int32_t max_batch_seqs = 1 << 17;
   uint8_t* d_arena = nullptr;
   std::unique_ptr<Arena> arena;
+  uint8_t* h_stage = nullptr;  // pinned staging of sets not yet copied
+  std::unique_ptr<Arena> stage;
+  hipStream_t copy_stream = nullptr;
+  std::vector<hipEvent_t> free_events;
+  std::deque<CopyRound> copies;  // in flight (worker thread only)
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<std::shared_ptr<Req>> pending;    // waiting for arena space
-  std::deque<std::shared_ptr<Req>> admitted;   // in the arena, not launched
+  std::deque<std::shared_ptr<SeqSet>> to_place;  // waiting for arena space
+  std::deque<std::shared_ptr<Req>> waiting;      // sequences not resident yet
+  std::deque<std::shared_ptr<Req>> ready;        // resident, not launched
   std::unordered_map<uint64_t, std::shared_ptr<Req>> all;
-  uint64_t next_ticket = 1;
-  int inflight = 0;  // admitted or running requests
+  std::unordered_map<uint64_t, std::shared_ptr<SeqSet>> sets;
+  uint64_t next_ticket = 1, next_set = 1;
+  int inflight = 0;  // requests admitted to run, not finished
+  int busy_slots = 0;
   bool stop = false;
   int sticky = XDROP_OK;
+  xdrop_server_counters st{};
   std::thread worker;
 
   void run();
   bool launch(Slot& s, std::vector<std::shared_ptr<Req>>& batch);
   void finish(Slot& s);
+  void drop_user(const std::shared_ptr<SeqSet>& set);  // under mu
+  void free_set(SeqSet& set);                          // under mu
+  std::shared_ptr<SeqSet> make_set(int alphabet, const uint8_t* seqs,
+                                   const int64_t* offsets, int32_t n_seqs);
 };
 
+void xdrop_server::free_set(SeqSet& set) {
+  if (set.placed) arena->release(set.arena_off, set.arena_bytes);
+  set.placed = false;
+  if (set.pin_off != NONE) stage->release(set.pin_off, set.bytes);
+  set.pin_off = NONE;
+  set.pageable.clear();
+  set.pageable.shrink_to_fit();
+  if (set.id) sets.erase(set.id);
+}
+
+void xdrop_server::drop_user(const std::shared_ptr<SeqSet>& set) {
+  if (--set->users == 0 && set->released) free_set(*set);
+}
+
+// A set with its sequences copied from the caller: into pinned staging if
+// it has room (the worker then moves them with an asynchronous copy), else
+// into ordinary memory.
+std::shared_ptr<SeqSet> xdrop_server::make_set(int alphabet,
+                                               const uint8_t* seqs,
+                                               const int64_t* offsets,
+                                               int32_t n_seqs) {
+  auto set = std::make_shared<SeqSet>();
+  set->alphabet = alphabet;
+  if (n_seqs > 0)
+    set->offsets.assign(offsets, offsets + n_seqs + 1);
+  else
+    set->offsets.assign(1, 0);
+  set->bytes = packed_bytes(alphabet, set->offsets.back());
+  set->arena_bytes = set->bytes + 64;
+  size_t off = NONE;
+  if (set->bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!stage->alloc(set->bytes, &off)) off = NONE;
+  }
+  if (off != NONE) {
+    std::memcpy(h_stage + off, seqs, set->bytes);  // (the range is ours)
+    set->pin_off = off;
+  } else if (set->bytes) {
+    set->pageable.assign(seqs, seqs + set->bytes);
+  }
+  return set;
+}
+
 bool xdrop_server::launch(Slot& s, std::vector<std::shared_ptr<Req>>& batch) {
-  // merged offsets: arena-absolute symbol offsets, a gap entry between
-  // requests that are not adjacent, and a last entry covering the arena
-  const int alpha = batch[0]->alphabet;
+  // merged offsets: arena-absolute symbol offsets of each set once, a gap
+  // entry after each, and a last entry covering every set
+  const int alpha = batch[0]->sc.alphabet;
   const int64_t spb = alpha == XDROP_DNA2 ? 4 : 1;  // symbols per byte
   int32_t nseq = 0, nseed = 0;
   int64_t* off = s.h_offsets;
   int64_t max_end = 0;
+  std::unordered_map<const SeqSet*, int32_t> first_seq;
   s.first_seed.clear();
   for (auto& r : batch) {
-    const int64_t base = (int64_t)r->arena_off * spb;
-    const int32_t first = nseq;
-    const int32_t rn = (int32_t)r->offsets.size() - 1;
-    for (int32_t i = 0; i <= rn; ++i) off[nseq + i] = base + r->offsets[i];
-    max_end = std::max(max_end, base + r->offsets[rn]);
-    nseq += rn + 1;  // the request's end entry starts a gap pseudo-sequence
+    const SeqSet* set = r->set.get();
+    const int32_t rn = (int32_t)set->offsets.size() - 1;
+    auto f = first_seq.find(set);
+    int32_t first;
+    if (f == first_seq.end()) {
+      const int64_t base = (int64_t)set->arena_off * spb;
+      first = nseq;
+      for (int32_t i = 0; i <= rn; ++i) off[nseq + i] = base + set->offsets[i];
+      max_end = std::max(max_end, base + set->offsets[rn]);
+      nseq += rn + 1;  // the set's end entry starts a gap pseudo-sequence
+      first_seq[set] = first;
+    } else {
+      first = f->second;
+    }
     s.first_seed.push_back(nseed);
     for (const auto& sd : r->seeds) {
       xdrop_seed t = sd;
@@ -160,7 +253,7 @@ bool xdrop_server::launch(Slot& s, std::vector<std::shared_ptr<Req>>& batch) {
       s.h_seeds[nseed++] = t;
     }
   }
-  // the last entry bounds the readable stream: past every request's end
+  // the last entry bounds the readable stream: past every set's end
   off[nseq] = std::max(max_end, off[nseq - 1]);
   s.n_seeds = nseed;
   s.batch = batch;
@@ -194,13 +287,14 @@ void xdrop_server::finish(Slot& s) {
       auto& r = b[i];
       const int32_t f = s.first_seed[i];
       r->results.assign(s.h_results + f, s.h_results + f + r->seeds.size());
-      arena->release(r->arena_off, r->arena_bytes);
-      r->seqs.clear();
-      r->seqs.shrink_to_fit();
+      drop_user(r->set);
+      r->set.reset();
       r->done = true;
       --inflight;
+      ++st.requests_done;
     }
     s.busy = false;
+    --busy_slots;
   }
   cv_done.notify_all();
   cv_work.notify_all();
@@ -208,54 +302,118 @@ void xdrop_server::finish(Slot& s) {
 
 void xdrop_server::run() {
   (void)hipSetDevice(device);
-  std::vector<std::shared_ptr<Req>> to_copy;
+  std::vector<std::shared_ptr<SeqSet>> to_copy;
   for (;;) {
-    // 1. admission: FIFO, as long as arena space and in-flight slots allow
+    bool progressed = false;
+    // 1. placement: sets in arrival order, as arena space allows
     to_copy.clear();
     {
       std::unique_lock<std::mutex> lk(mu);
       if (stop) break;
-      while (!pending.empty() && inflight < max_inflight) {
-        auto& r = pending.front();
+      while (!to_place.empty()) {
+        auto& set = to_place.front();
+        if (set->released && set->users == 0) {  // dropped before placement
+          free_set(*set);
+          to_place.pop_front();
+          continue;
+        }
         size_t off;
-        if (!arena->alloc(r->arena_bytes, &off)) break;
-        r->arena_off = off;
-        to_copy.push_back(r);
-        admitted.push_back(r);
-        pending.pop_front();
-        ++inflight;
+        if (!arena->alloc(set->arena_bytes, &off)) break;
+        set->arena_off = off;
+        set->placed = true;
+        to_copy.push_back(set);
+        to_place.pop_front();
       }
     }
-    for (auto& r : to_copy) {
-      // staged through the copy in host memory (synchronous for pageable)
-      hipError_t e = hipMemcpy(d_arena + r->arena_off, r->seqs.data(),
-                               r->seqs.size(), hipMemcpyHostToDevice);
+    // 2. asynchronous copies of the placed sets on the copy stream (from
+    // pinned staging; a set held in ordinary memory is staged by the
+    // runtime), one event per round
+    if (!to_copy.empty()) {
+      CopyRound round;
+      hipError_t e = hipSuccess;
+      for (auto& set : to_copy) {
+        const uint8_t* src = set->pin_off != NONE ? h_stage + set->pin_off
+                                                  : set->pageable.data();
+        if (set->bytes && e == hipSuccess)
+          e = hipMemcpyAsync(d_arena + set->arena_off, src, set->bytes,
+                             hipMemcpyHostToDevice, copy_stream);
+        round.sets.push_back(set);
+      }
+      if (free_events.empty()) {
+        hipEvent_t ev;
+        if (e == hipSuccess)
+          e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) free_events.push_back(ev);
+      }
+      if (e == hipSuccess) {
+        round.ev = free_events.back();
+        free_events.pop_back();
+        e = hipEventRecord(round.ev, copy_stream);
+      }
       if (e != hipSuccess) {
         std::lock_guard<std::mutex> lk(mu);
         sticky = XDROP_E_DEVICE;
       }
+      copies.push_back(std::move(round));
+      progressed = true;
     }
-    // 2. completions
-    bool progressed = !to_copy.empty();
+    // 3. copies done: the sets are resident
+    while (!copies.empty() && copies.front().ev &&
+           hipEventQuery(copies.front().ev) == hipSuccess) {
+      CopyRound round = std::move(copies.front());
+      copies.pop_front();
+      free_events.push_back(round.ev);
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto& set : round.sets) {
+        set->resident = true;
+        st.h2d_bytes += (int64_t)set->bytes;
+        if (set->pin_off != NONE) stage->release(set->pin_off, set->bytes);
+        set->pin_off = NONE;
+        set->pageable.clear();
+        set->pageable.shrink_to_fit();
+        if (set->released && set->users == 0) free_set(*set);
+      }
+      progressed = true;
+    }
+    // 4. admission: requests whose sequences are resident, in arrival
+    // order, as far as the in-flight limit allows
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto it = waiting.begin();
+           it != waiting.end() && inflight < max_inflight;) {
+        if ((*it)->set->resident) {
+          if (busy_slots > 0) ++st.admitted_while_busy;
+          ready.push_back(*it);
+          it = waiting.erase(it);
+          ++inflight;
+          progressed = true;
+        } else {
+          ++it;
+        }
+      }
+    }
+    // 5. completions
     for (auto& s : slots) {
       if (s.busy && hipEventQuery(s.done) == hipSuccess) {
         finish(s);
         progressed = true;
       }
     }
-    // 3. launches: micro-batches of admitted requests with one scoring
+    // 6. launches: micro-batches of ready requests with one scoring
     for (auto& s : slots) {
       if (s.busy) continue;
       std::vector<std::shared_ptr<Req>> batch;
       {
         std::lock_guard<std::mutex> lk(mu);
-        if (admitted.empty()) break;
+        if (ready.empty()) break;
         int32_t ns = 0, nq = 0;
-        auto it = admitted.begin();
-        while (it != admitted.end()) {
+        std::unordered_set<const SeqSet*> in_batch;
+        auto it = ready.begin();
+        while (it != ready.end()) {
           auto& r = *it;
           const int32_t rs = (int32_t)r->seeds.size();
-          const int32_t rq = (int32_t)r->offsets.size();
+          const int32_t rq = in_batch.count(r->set.get())
+                                 ? 0 : (int32_t)r->set->offsets.size();
           if (!batch.empty() &&
               (!same_scoring(*batch[0], *r) || ns + rs > max_batch_seeds ||
                nq + rq + 1 > max_batch_seqs)) {
@@ -263,20 +421,29 @@ void xdrop_server::run() {
             continue;
           }
           batch.push_back(r);
+          in_batch.insert(r->set.get());
           ns += rs;
           nq += rq;
-          it = admitted.erase(it);
+          it = ready.erase(it);
           if (ns >= max_batch_seeds) break;
+        }
+        if (!batch.empty()) {
+          ++busy_slots;
+          ++st.batches_launched;
+          st.max_batches_in_flight =
+              std::max<int64_t>(st.max_batches_in_flight, busy_slots);
         }
       }
       if (batch.empty()) break;
       if (!launch(s, batch)) {
         std::lock_guard<std::mutex> lk(mu);
         sticky = XDROP_E_DEVICE;
+        --busy_slots;
         for (auto& r : batch) {
           r->status = XDROP_E_DEVICE;
           r->done = true;
-          arena->release(r->arena_off, r->arena_bytes);
+          drop_user(r->set);
+          r->set.reset();
           --inflight;
         }
         cv_done.notify_all();
@@ -285,13 +452,12 @@ void xdrop_server::run() {
     }
     if (!progressed) {
       std::unique_lock<std::mutex> lk(mu);
-      bool any_busy = false;
-      for (auto& s : slots) any_busy |= s.busy;
-      if (any_busy)
+      if (busy_slots > 0 || !copies.empty())
         cv_work.wait_for(lk, std::chrono::microseconds(20));
-      else if (pending.empty() && admitted.empty())
-        cv_work.wait_for(lk, std::chrono::milliseconds(5),
-                         [&] { return stop || !pending.empty(); });
+      else if (to_place.empty() && waiting.empty() && ready.empty())
+        cv_work.wait_for(lk, std::chrono::milliseconds(5), [&] {
+          return stop || !to_place.empty() || !waiting.empty();
+        });
     }
   }
   for (auto& s : slots)
@@ -299,6 +465,10 @@ void xdrop_server::run() {
       (void)hipEventSynchronize(s.done);
       finish(s);
     }
+  (void)hipStreamSynchronize(copy_stream);
+  for (auto& round : copies)
+    if (round.ev) free_events.push_back(round.ev);
+  copies.clear();
 }
 
 extern "C" {
@@ -311,7 +481,8 @@ int xdrop_server_create(int device, size_t hbm_budget_bytes,
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
     return XDROP_E_INVALID;
   if (opts && (opts->max_inflight < 0 || opts->streams < 0 ||
-               opts->streams > 16 || opts->arena_mib < 0))
+               opts->streams > 16 || opts->arena_mib < 0 ||
+               opts->staging_mib < 0))
     return XDROP_E_INVALID;
   const int nslots = opts && opts->streams ? opts->streams : 4;
   // per stream: staging of one micro-batch and one library context
@@ -323,10 +494,11 @@ int xdrop_server_create(int device, size_t hbm_budget_bytes,
     if (((size_t)opts->arena_mib << 20) > arena_bytes) return XDROP_E_BUDGET;
     arena_bytes = (size_t)opts->arena_mib << 20;
   }
+  const size_t stage_bytes =
+      (size_t)(opts && opts->staging_mib ? opts->staging_mib : 64) << 20;
   auto* s = new (std::nothrow) xdrop_server();
   if (!s) return XDROP_E_NOMEM;
   s->device = device;
-  s->budget = hbm_budget_bytes;
   if (opts && opts->max_inflight > 0) s->max_inflight = opts->max_inflight;
   if (hipSetDevice(device) != hipSuccess) {
     delete s;
@@ -337,6 +509,15 @@ int xdrop_server_create(int device, size_t hbm_budget_bytes,
     return XDROP_E_NOMEM;
   }
   s->arena.reset(new Arena(arena_bytes));
+  if (hipHostMalloc(&s->h_stage, stage_bytes, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) !=
+          hipSuccess) {
+    s->stop = true;
+    xdrop_server_destroy(s);
+    return XDROP_E_NOMEM;
+  }
+  s->stage.reset(new Arena(stage_bytes));
   s->slots.resize(nslots);
   for (auto& sl : s->slots) {
     bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) ==
@@ -371,12 +552,60 @@ int xdrop_server_create(int device, size_t hbm_budget_bytes,
   return XDROP_OK;
 }
 
+static int check_set_args(xdrop_server* s, int alphabet,
+                          const int64_t* offsets, int32_t n_seqs) {
+  if (alphabet != XDROP_DNA2 && alphabet != XDROP_BYTE) return XDROP_E_INVALID;
+  if (n_seqs < 0 || (n_seqs > 0 && !offsets)) return XDROP_E_INVALID;
+  if (n_seqs + 1 > s->max_batch_seqs) return XDROP_E_BUDGET;
+  for (int32_t i = 0; i < n_seqs; ++i)
+    if (offsets[i] < 0 || offsets[i + 1] < offsets[i]) return XDROP_E_INVALID;
+  if (n_seqs > 0 && offsets[0] != 0) return XDROP_E_INVALID;
+  const int64_t syms = n_seqs > 0 ? offsets[n_seqs] : 0;
+  if (packed_bytes(alphabet, syms) + 64 > s->arena->cap()) return XDROP_E_BUDGET;
+  return XDROP_OK;
+}
+
+int xdrop_server_put_sequences(xdrop_server* s, const uint8_t* seqs,
+                               const int64_t* offsets, int32_t n_seqs,
+                               int32_t alphabet, uint64_t* set_id) {
+  if (!s || !set_id) return XDROP_E_INVALID;
+  int rc = check_set_args(s, alphabet, offsets, n_seqs);
+  if (rc != XDROP_OK) return rc;
+  const int64_t syms = n_seqs > 0 ? offsets[n_seqs] : 0;
+  if (syms > 0 && !seqs) return XDROP_E_INVALID;
+  auto set = s->make_set(alphabet, seqs, offsets, n_seqs);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->sticky != XDROP_OK) {
+      s->free_set(*set);
+      return s->sticky;
+    }
+    set->id = s->next_set++;
+    *set_id = set->id;
+    s->sets[set->id] = set;
+    s->to_place.push_back(set);
+  }
+  s->cv_work.notify_all();
+  return XDROP_OK;
+}
+
+int xdrop_server_release_sequences(xdrop_server* s, uint64_t set_id) {
+  if (!s) return XDROP_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->sets.find(set_id);
+  if (it == s->sets.end() || it->second->released) return XDROP_E_INVALID;
+  auto set = it->second;
+  set->released = true;
+  // freed now if resident and unused; a set still waiting for space or
+  // being copied is freed by the worker when that step ends
+  if (set->users == 0 && set->resident) s->free_set(*set);
+  return XDROP_OK;
+}
+
 int xdrop_server_submit(xdrop_server* s, const xdrop_request* r,
                         uint64_t* ticket) {
   if (!s || !r || !ticket) return XDROP_E_INVALID;
-  if (r->n_seqs < 0 || r->n_seeds < 0 || (r->n_seqs > 0 && !r->offsets) ||
-      (r->n_seeds > 0 && !r->seeds))
-    return XDROP_E_INVALID;
+  if (r->n_seeds < 0 || (r->n_seeds > 0 && !r->seeds)) return XDROP_E_INVALID;
   const xdrop_scoring& sc = r->scoring;
   if (sc.alphabet != XDROP_DNA2 && sc.alphabet != XDROP_BYTE)
     return XDROP_E_INVALID;
@@ -384,24 +613,17 @@ int xdrop_server_submit(xdrop_server* s, const xdrop_request* r,
                                 : (sc.alphabet_size < 1 || sc.alphabet_size > 32))
     return XDROP_E_INVALID;
   if (sc.gap > 0 || sc.X < 0) return XDROP_E_INVALID;
-  if (r->n_seqs + 1 > s->max_batch_seqs || r->n_seeds > s->max_batch_seeds)
-    return XDROP_E_BUDGET;
-  for (int32_t i = 0; i < r->n_seqs; ++i)
-    if (r->offsets[i] < 0 || r->offsets[i + 1] < r->offsets[i])
-      return XDROP_E_INVALID;
-  if (r->n_seqs > 0 && r->offsets[0] != 0) return XDROP_E_INVALID;
+  if (r->n_seeds > s->max_batch_seeds) return XDROP_E_BUDGET;
   auto q = std::make_shared<Req>();
-  q->alphabet = sc.alphabet;
-  const int64_t syms = r->n_seqs > 0 ? r->offsets[r->n_seqs] : 0;
-  const size_t bytes = sc.alphabet == XDROP_DNA2 ? (size_t)((syms + 15) / 16) * 4
-                                                 : (size_t)((syms + 3) / 4) * 4;
-  q->arena_bytes = bytes + 64;
-  if (q->arena_bytes > s->arena->cap()) return XDROP_E_BUDGET;
-  q->seqs.assign(r->seqs, r->seqs + bytes);
-  if (r->n_seqs > 0)
-    q->offsets.assign(r->offsets, r->offsets + r->n_seqs + 1);
-  else
-    q->offsets.assign(1, 0);
+  std::shared_ptr<SeqSet> own;
+  if (!r->seq_set) {
+    int rc = check_set_args(s, sc.alphabet, r->offsets, r->n_seqs);
+    if (rc != XDROP_OK) return rc;
+    const int64_t syms = r->n_seqs > 0 ? r->offsets[r->n_seqs] : 0;
+    if (syms > 0 && !r->seqs) return XDROP_E_INVALID;
+    own = s->make_set(sc.alphabet, r->seqs, r->offsets, r->n_seqs);
+    own->released = true;  // lives as long as the request
+  }
   q->seeds.assign(r->seeds, r->seeds + r->n_seeds);
   q->sc = sc;
   if (sc.matrix)
@@ -409,14 +631,43 @@ int xdrop_server_submit(xdrop_server* s, const xdrop_request* r,
   q->sc.matrix = nullptr;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->sticky != XDROP_OK) return s->sticky;
+    if (s->sticky != XDROP_OK) {
+      if (own) s->free_set(*own);
+      return s->sticky;
+    }
+    if (own) {
+      q->set = own;
+    } else {
+      auto it = s->sets.find(r->seq_set);
+      if (it == s->sets.end() || it->second->released ||
+          it->second->alphabet != sc.alphabet)
+        return XDROP_E_INVALID;
+      q->set = it->second;
+      // the bytes of the sequences the seeds use that this request does not
+      // copy
+      const auto& off = q->set->offsets;
+      const int32_t ns = (int32_t)off.size() - 1;
+      std::unordered_set<int32_t> used;
+      for (const auto& z : q->seeds) {
+        if (z.q >= 0 && z.q < ns) used.insert(z.q);
+        if (z.t >= 0 && z.t < ns) used.insert(z.t);
+      }
+      for (int32_t i : used)
+        s->st.reused_bytes +=
+            (int64_t)packed_bytes(sc.alphabet, off[i + 1] - off[i]);
+    }
+    q->set->users++;
     q->ticket = s->next_ticket++;
     *ticket = q->ticket;
     s->all[q->ticket] = q;
+    ++s->st.requests_submitted;
     if (q->seeds.empty()) {
       q->done = true;  // nothing to compute
+      s->drop_user(q->set);
+      q->set.reset();
     } else {
-      s->pending.push_back(q);
+      if (own) s->to_place.push_back(own);
+      s->waiting.push_back(q);
     }
   }
   s->cv_work.notify_all();
@@ -457,6 +708,14 @@ int xdrop_server_wait(xdrop_server* s, uint64_t ticket, xdrop_result* out,
   return take_result(s, ticket, out, lk, true, timeout_ns);
 }
 
+int xdrop_server_stats(xdrop_server* s, xdrop_server_counters* out) {
+  if (!s || !out) return XDROP_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  out->batches_in_flight = s->busy_slots;
+  return XDROP_OK;
+}
+
 int xdrop_server_destroy(xdrop_server* s) {
   if (!s) return XDROP_E_INVALID;
   {
@@ -478,6 +737,12 @@ int xdrop_server_destroy(xdrop_server* s) {
     if (sl.h_seeds) (void)hipHostFree(sl.h_seeds);
     if (sl.h_results) (void)hipHostFree(sl.h_results);
   }
+  if (s->copy_stream) {
+    (void)hipStreamSynchronize(s->copy_stream);
+    (void)hipStreamDestroy(s->copy_stream);
+  }
+  for (auto ev : s->free_events) (void)hipEventDestroy(ev);
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
   if (s->d_arena) (void)hipFree(s->d_arena);
   delete s;
   return XDROP_OK;

@@ -298,14 +298,10 @@ def concat(a: Batch, b: Batch, meta=None) -> Batch:
                  meta if meta is not None else dict(a.meta))
 
 
-def request_stream_pooled(rng, n_requests: int, mean_gap_s: float,
-                          max_pairs=4096, pool_pairs=8192):
-    """As request_stream, but each request takes a contiguous run of pairs
-    (cyclic) at a random start from one of two pools generated once: DNA
-    pairs of the 1k generator and protein pairs of the protein generator.
-    Request sizes, arrivals and the DNA/protein mix follow the same laws; the
-    pools make long streams cheap to generate (pairs repeat across
-    requests).  Yields (arrival_time_s, Batch, Scheme)."""
+def request_pools(rng, pool_pairs=8192):
+    """The two pools the pooled request stream draws from: DNA pairs of the
+    1k generator and protein pairs of the protein generator.  Returns
+    [(pool Batch, Scheme), (pool Batch, Scheme)]."""
     dna_scheme = Scheme(4, 1, -1, -1, 15)
     prot_scheme = Scheme(20, gap=-2, X=49,
                          matrix=stand_in_substitution_matrix())
@@ -315,15 +311,37 @@ def request_stream_pooled(rng, n_requests: int, mean_gap_s: float,
     L = rng.integers(50, 1001, pool_pairs)
     prot_pool = _assemble(protein_pairs(rng, pool_pairs, L, 6, 0.5), 20,
                           {"pool": "protein"})
+    return [(dna_pool, dna_scheme), (prot_pool, prot_scheme)]
+
+
+def request_refs(rng, n_requests: int, mean_gap_s: float, pool_pairs: int,
+                 max_pairs=4096):
+    """Arrival times and pair selections of the pooled request stream: each
+    request takes a contiguous run of pairs (cyclic) at a random start in
+    pool 0 (DNA) or 1 (protein) with probability 1/2; sizes follow the
+    request-size law.  Yields (arrival_time_s, pool index, pair indices)."""
     t = 0.0
-    for r in range(n_requests):
+    for _ in range(n_requests):
         t += float(rng.exponential(mean_gap_s))
         size = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(max_pairs + 1)))),
                            1, max_pairs))
-        pool, scheme = ((dna_pool, dna_scheme) if rng.random() < 0.5
-                        else (prot_pool, prot_scheme))
+        which = 0 if rng.random() < 0.5 else 1
         start = int(rng.integers(0, pool_pairs))
-        idx = (start + np.arange(size)) % pool_pairs
+        yield t, which, (start + np.arange(size)) % pool_pairs
+
+
+def request_stream_pooled(rng, n_requests: int, mean_gap_s: float,
+                          max_pairs=4096, pool_pairs=8192):
+    """As request_stream, but each request takes a contiguous run of pairs
+    (cyclic) at a random start from one of two pools generated once
+    (request_pools).  Request sizes, arrivals and the DNA/protein mix follow
+    the same laws; the pools make long streams cheap to generate (pairs
+    repeat across requests).  Yields (arrival_time_s, Batch, Scheme), the
+    Batch holding its own copy of the pairs' sequences."""
+    pools = request_pools(rng, pool_pairs)
+    for r, (t, which, idx) in enumerate(
+            request_refs(rng, n_requests, mean_gap_s, pool_pairs, max_pairs)):
+        pool, scheme = pools[which]
         b = pool.subset(idx)
         b.meta = {"request": r}
         yield t, b, scheme

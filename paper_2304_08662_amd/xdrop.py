@@ -85,14 +85,23 @@ class Request(ctypes.Structure):
                 ("n_seqs", ctypes.c_int32),
                 ("seeds", ctypes.c_void_p),
                 ("n_seeds", ctypes.c_int32),
-                ("scoring", Scoring)]
+                ("scoring", Scoring),
+                ("seq_set", ctypes.c_uint64)]
 
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32),
                 ("streams", ctypes.c_int32),
                 ("arena_mib", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("staging_mib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "requests_submitted", "requests_done", "batches_launched",
+        "batches_in_flight", "max_batches_in_flight", "admitted_while_busy",
+        "h2d_bytes", "reused_bytes")] + [("reserved", ctypes.c_int64 * 8)]
 
 
 EXPORTS = ["xdrop_ctx_create", "xdrop_ctx_destroy", "xdrop_extend_batch",
@@ -102,20 +111,16 @@ EXPORTS = ["xdrop_ctx_create", "xdrop_ctx_destroy", "xdrop_extend_batch",
            "xdrop_extend_batch_graph",
            "xdrop_last_stats", "xdrop_server_create", "xdrop_server_submit",
            "xdrop_server_poll", "xdrop_server_wait", "xdrop_server_destroy",
+           "xdrop_server_put_sequences", "xdrop_server_release_sequences",
+           "xdrop_server_stats",
            "xdrop_strerror"]
 
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libxdrop.so (raises if it is missing: there is no fallback)."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(path):
-        raise RuntimeError(f"{path} is missing; build it with "
-                           "paper_2304_08662_amd/build.py")
-    lib = ctypes.CDLL(path)
+def bind(lib):
+    """Declare the argument and result types of every entry point of a
+    loaded copy of the library."""
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     lib.xdrop_strerror.restype = ctypes.c_char_p
     lib.xdrop_strerror.argtypes = [ctypes.c_int]
@@ -147,11 +152,26 @@ def load_library(path: str = LIB_PATH):
     lib.xdrop_server_wait.argtypes = [vp, ctypes.c_uint64, vp,
                                       ctypes.c_int64]
     lib.xdrop_server_destroy.argtypes = [vp]
+    lib.xdrop_server_put_sequences.argtypes = [
+        vp, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.xdrop_server_release_sequences.argtypes = [vp, ctypes.c_uint64]
+    lib.xdrop_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     for f in EXPORTS:
         if f != "xdrop_strerror":
             getattr(lib, f).restype = ctypes.c_int
-    _lib = lib
     return lib
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libxdrop.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing; build it with "
+                           "paper_2304_08662_amd/build.py")
+    _lib = bind(ctypes.CDLL(path))
+    return _lib
 
 
 def strerror(status: int) -> str:
@@ -208,8 +228,8 @@ def _ptr(t):
 class Context:
     """A library context on one device (owns the device workspace)."""
 
-    def __init__(self, device: int = 0, device_tier_slots: int = 0):
-        self.lib = load_library()
+    def __init__(self, device: int = 0, device_tier_slots: int = 0, lib=None):
+        self.lib = lib if lib is not None else load_library()
         h = ctypes.c_void_p()
         o = CtxOpts(device_tier_slots)
         _check(self.lib.xdrop_ctx_create(device, ctypes.byref(o), ctypes.byref(h)),
@@ -303,28 +323,59 @@ class Server:
     """Continuous-batching server (host API of include/xdrop.h)."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 64 << 30,
-                 max_inflight: int = 0, streams: int = 0, arena_mib: int = 0):
-        self.lib = load_library()
+                 max_inflight: int = 0, streams: int = 0, arena_mib: int = 0,
+                 staging_mib: int = 0, lib=None):
+        self.lib = lib if lib is not None else load_library()
         h = ctypes.c_void_p()
-        so = ServerOpts(max_inflight, streams, arena_mib)
+        so = ServerOpts(max_inflight, streams, arena_mib, staging_mib)
         _check(self.lib.xdrop_server_create(device, budget_bytes,
                                             ctypes.byref(so), ctypes.byref(h)),
                "xdrop_server_create")
         self.handle = h
 
-    def submit(self, packed: np.ndarray, offsets: np.ndarray,
-               seeds: np.ndarray, scoring: ScoringSpec) -> int:
-        packed = np.ascontiguousarray(packed, dtype=np.uint8)
-        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    def submit(self, packed: np.ndarray | None, offsets: np.ndarray | None,
+               seeds: np.ndarray, scoring: ScoringSpec,
+               seq_set: int = 0) -> int:
+        """A request over its own sequences (packed, offsets), or over a
+        resident set (seq_set from put_sequences; packed and offsets
+        None)."""
         seeds = np.ascontiguousarray(seeds).astype(SEED_DTYPE, copy=False)
-        req = Request(packed.ctypes.data, offsets.ctypes.data,
-                      len(offsets) - 1, seeds.ctypes.data, len(seeds),
-                      scoring.c())
+        if seq_set:
+            req = Request(None, None, 0, seeds.ctypes.data, len(seeds),
+                          scoring.c(), seq_set)
+        else:
+            packed = np.ascontiguousarray(packed, dtype=np.uint8)
+            offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+            req = Request(packed.ctypes.data, offsets.ctypes.data,
+                          len(offsets) - 1, seeds.ctypes.data, len(seeds),
+                          scoring.c(), 0)
         t = ctypes.c_uint64()
         _check(self.lib.xdrop_server_submit(self.handle, ctypes.byref(req),
                                             ctypes.byref(t)),
                "xdrop_server_submit")
         return int(t.value)
+
+    def put_sequences(self, packed: np.ndarray, offsets: np.ndarray,
+                      alphabet: int) -> int:
+        """Register sequences that requests seed against (copied once)."""
+        packed = np.ascontiguousarray(packed, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        sid = ctypes.c_uint64()
+        _check(self.lib.xdrop_server_put_sequences(
+            self.handle, packed.ctypes.data, offsets.ctypes.data,
+            len(offsets) - 1, alphabet, ctypes.byref(sid)),
+            "xdrop_server_put_sequences")
+        return int(sid.value)
+
+    def release_sequences(self, set_id: int):
+        _check(self.lib.xdrop_server_release_sequences(self.handle, set_id),
+               "xdrop_server_release_sequences")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self.lib.xdrop_server_stats(self.handle, ctypes.byref(st)),
+               "xdrop_server_stats")
+        return {n: int(getattr(st, n)) for n, _ in ServerStats._fields_[:-1]}
 
     def poll(self, ticket: int, n_seeds: int):
         out = np.zeros(n_seeds, dtype=RESULT_DTYPE)

@@ -49,6 +49,8 @@ def build(csrc: str | None = None, out: str = LIB, extra=(),
         f.write(k)
     srcs = [kout, os.path.join(csrc, "xdrop_host.cpp"),
             os.path.join(HERE, "emu_runtime.cpp")]
+    if os.path.exists(os.path.join(csrc, "xdrop_server.cpp")):
+        srcs.append(os.path.join(csrc, "xdrop_server.cpp"))
     cmd = [CXX, "-O2", "-g", "-std=c++17", "-fPIC", "-shared",
            "-Wno-unused-command-line-argument", "-I", HERE, "-I",
            include or os.path.join(ROOT, "include"), "-I", csrc, *extra, *srcs, "-o", out + ".tmp", "-lpthread"]

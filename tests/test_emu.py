@@ -194,3 +194,14 @@ def test_noalloc_equals_extend_batch_twice(emu):
         got = emu.run(batch, sc, noalloc=True)
         assert not compare(got, ref)
         assert not compare(got, oracle_run(batch, scheme))
+
+
+def test_seeds_share_sequences(emu):
+    from tests.xdrop_testutil import shared_sequence_batches
+    rng = np.random.default_rng([82, 4])
+    shared, unique = shared_sequence_batches(rng, n_seeds=60)
+    scheme = inputs.Scheme(4, 1, -1, -1, 20)
+    sc = product_scoring(scheme)
+    g = emu.run(shared, sc)
+    assert not compare(g, emu.run(unique, sc))
+    assert not compare(g, oracle_run(shared, scheme))

@@ -275,6 +275,24 @@ def test_long_byte_codes_wrap_rings(runner):
         assert not compare(runner.run(batch, scheme), oracle_run(batch, scheme)), X
 
 
+@pytest.mark.parametrize("alphabet", [4, 20])
+def test_seeds_share_sequences(runner, alphabet):
+    """Many seeds over a few resident sequences (several per pair, one
+    sequence against several others) give the results of the same seeds on
+    their own copies of the sequences, and the oracle's."""
+    from tests.xdrop_testutil import shared_sequence_batches
+    rng = np.random.default_rng([82, alphabet])
+    shared, unique = shared_sequence_batches(rng, alphabet=alphabet)
+    if alphabet == 4:
+        scheme = inputs.Scheme(4, 1, -1, -1, 20)
+    else:
+        scheme = inputs.Scheme(20, gap=-2, X=49,
+                               matrix=inputs.stand_in_substitution_matrix())
+    g_shared = runner.run(shared, scheme)
+    assert not compare(g_shared, runner.run(unique, scheme))
+    assert not compare(g_shared, oracle_run(shared, scheme))
+
+
 def test_statuses(runner):
     from paper_2304_08662_amd import xdrop
     rng = np.random.default_rng(25)

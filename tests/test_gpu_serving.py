@@ -1,11 +1,15 @@
 """Serving loop: continuous batching of requests of mixed size and alphabet;
 every result must equal the oracle's and the request's result when served
-alone (bit-exact)."""
+alone (bit-exact), also for requests that arrive while other micro-batches
+run on the device and for requests that seed against resident sequence
+sets."""
+import time
+
 import numpy as np
 import pytest
 
 from paper_2304_08662_amd import inputs
-from tests.xdrop_testutil import FIELDS, oracle_run, product_scoring
+from tests.xdrop_testutil import FIELDS, make_batch, oracle_run, product_scoring
 
 pytestmark = pytest.mark.gpu
 
@@ -28,6 +32,11 @@ def _same(a, b):
                for f in FIELDS)
 
 
+def _alone(srv, b, s):
+    t = srv.submit(_packed(b), b.offsets, b.seeds, product_scoring(s))
+    return srv.wait(t, len(b.seeds), 120)
+
+
 def test_alone_equals_mix_equals_oracle(xd):
     rng = inputs.rng_for(5, 1)
     reqs = [(b, s) for _, b, s in inputs.request_stream(rng, 24, 0.0,
@@ -39,11 +48,96 @@ def test_alone_equals_mix_equals_oracle(xd):
     mixed = [srv.wait(t, len(b.seeds), 120) for t, (b, _) in zip(tickets, reqs)]
     # alone: one request in flight at a time
     for (b, s), m in zip(reqs, mixed):
-        t = srv.submit(_packed(b), b.offsets, b.seeds, product_scoring(s))
-        alone = srv.wait(t, len(b.seeds), 120)
+        alone = _alone(srv, b, s)
         assert m is not None and alone is not None
         assert _same(m, alone)
         assert _same(m, oracle_run(b, s))
+    srv.close()
+
+
+def _long_request(seed, n_pairs):
+    """Pairs of 50-100 kb at 15% edits (X = 15): each extension is a chain
+    of ~100,000 antidiagonals, so a micro-batch of them stays on the device
+    for milliseconds."""
+    rng = inputs.rng_for(9, seed)
+    L = rng.integers(50000, 100001, n_pairs)
+    b = inputs._assemble(inputs.dna_pairs(rng, n_pairs, L, 0.15, 17, 1.0,
+                                          seed_at_mid=True), 4, {})
+    return b, inputs.Scheme(4, 1, -1, -1, 15)
+
+
+def test_arrivals_while_micro_batches_run(xd):
+    """Requests submitted while earlier micro-batches are on the device are
+    admitted and run beside them; each result equals the request served
+    alone and the oracle."""
+    srv = xd.Server(0, budget_bytes=4 << 30, streams=4)
+    first = _long_request(1, 6)
+    rng = inputs.rng_for(5, 3)
+    later = [_long_request(2 + i, 3) for i in range(3)]
+    later += [(b, s) for _, b, s in inputs.request_stream(rng, 12, 0.0,
+                                                          max_pairs=200)]
+    t0 = srv.submit(_packed(first[0]), first[0].offsets, first[0].seeds,
+                    product_scoring(first[1]))
+    deadline = time.time() + 30
+    while srv.stats()["batches_in_flight"] == 0 and time.time() < deadline:
+        time.sleep(1e-4)
+    assert srv.stats()["batches_in_flight"] >= 1
+    tickets = []
+    for b, s in later:  # staggered arrivals while the first batch runs
+        tickets.append(srv.submit(_packed(b), b.offsets, b.seeds,
+                                  product_scoring(s)))
+        time.sleep(5e-4)
+    mixed = [srv.wait(t0, len(first[0].seeds), 120)]
+    mixed += [srv.wait(t, len(b.seeds), 120) for t, (b, _) in zip(tickets, later)]
+    st = srv.stats()
+    assert st["max_batches_in_flight"] >= 2, st
+    assert st["admitted_while_busy"] >= 1, st
+    for (b, s), m in zip([first] + later, mixed):
+        assert m is not None
+        assert _same(m, _alone(srv, b, s))
+        assert _same(m, oracle_run(b, s))
+    srv.close()
+
+
+def test_requests_on_resident_sequence_sets(xd):
+    """Requests seed against a registered set of sequences (copied once):
+    results equal the same seeds run on their own copies of the sequences
+    and the oracle; the copied bytes count the set once."""
+    rng = np.random.default_rng(80)
+    pool = make_batch([(rng.integers(0, 20, int(rng.integers(100, 900))).astype(np.uint8),
+                        rng.integers(0, 20, int(rng.integers(100, 900))).astype(np.uint8),
+                        0, 0, 0) for _ in range(64)], 20)
+    codes = pool.codes.copy()
+    scheme = inputs.Scheme(20, gap=-2, X=49,
+                           matrix=inputs.stand_in_substitution_matrix())
+    srv = xd.Server(0, budget_bytes=2 << 30)
+    sid = srv.put_sequences(codes, pool.offsets, xd.BYTE)
+    L = np.diff(pool.offsets)
+    reqs = []
+    for r in range(10):
+        n = int(rng.integers(1, 40))
+        q = rng.integers(0, pool.n_seqs, n)
+        t = rng.integers(0, pool.n_seqs, n)
+        k = np.minimum(np.minimum(L[q], L[t]), 6)
+        qp = (rng.random(n) * (L[q] - k + 1)).astype(np.int64)
+        tp = (rng.random(n) * (L[t] - k + 1)).astype(np.int64)
+        sd = np.zeros(n, dtype=xd.SEED_DTYPE)
+        sd["q"], sd["t"], sd["q_pos"], sd["t_pos"], sd["k"] = q, t, qp, tp, k
+        reqs.append(sd)
+    sc = product_scoring(scheme)
+    tickets = [srv.submit(None, None, sd, sc, seq_set=sid) for sd in reqs]
+    got = [srv.wait(tk, len(sd), 120) for tk, sd in zip(tickets, reqs)]
+    st = srv.stats()
+    assert st["reused_bytes"] > 0
+    assert st["h2d_bytes"] >= len(codes)
+    for sd, g in zip(reqs, got):
+        b = inputs.Batch(codes, pool.offsets, sd, 20)
+        assert _same(g, oracle_run(b, scheme))
+        own = srv.submit(codes, pool.offsets, sd, sc)  # its own copy
+        assert _same(g, srv.wait(own, len(sd), 120))
+    srv.release_sequences(sid)
+    with pytest.raises(xd.XdropError):
+        srv.submit(None, None, reqs[0], sc, seq_set=sid)
     srv.close()
 
 

@@ -30,20 +30,7 @@ class EmuLib:
             path = emu_build.LIB
             if not os.path.exists(path):
                 build()
-        lib = ctypes.CDLL(path)
-        vp, i32 = ctypes.c_void_p, ctypes.c_int32
-        lib.xdrop_ctx_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
-        lib.xdrop_ctx_destroy.argtypes = [vp]
-        args = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(xdrop.Scoring),
-                ctypes.POINTER(xdrop.Options), vp, vp]
-        lib.xdrop_extend_batch.argtypes = args
-        lib.xdrop_extend_batch_noalloc.argtypes = args
-        lib.xdrop_last_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
-                                         i32]
-        for f in ("xdrop_ctx_create", "xdrop_ctx_destroy",
-                  "xdrop_extend_batch", "xdrop_extend_batch_noalloc",
-                  "xdrop_last_stats"):
-            getattr(lib, f).restype = ctypes.c_int
+        lib = xdrop.bind(ctypes.CDLL(path))
         self.lib = lib
         h = ctypes.c_void_p()
         rc = lib.xdrop_ctx_create(0, None, ctypes.byref(h))

@@ -82,3 +82,33 @@ def compare(gpu, ref, idx=None):
 
 def make_batch(pairs, alphabet, meta=None):
     return inputs._assemble(pairs, alphabet, meta or {})
+
+
+def shared_sequence_batches(rng, n_seqs=24, n_seeds=160, alphabet=4):
+    """Seeds that share sequences: n_seqs sequences (half of them edited
+    copies of the other half), n_seeds seeds drawn over them, several seeds
+    on one pair at different positions and one sequence against several
+    others.  Returns (shared batch, unique-copy batch with one fresh copy of
+    both sequences per seed)."""
+    from paper_2304_08662_amd import inputs
+    half = n_seqs // 2
+    seqs = [rng.integers(0, alphabet, int(rng.integers(150, 1200))).astype(np.uint8)
+            for _ in range(half)]
+    seqs += [inputs.mutate(rng, s, 0.05, 0.03, 0.03, alphabet)[0] for s in seqs]
+    L = np.array([len(s) for s in seqs])
+    offs = np.zeros(n_seqs + 1, dtype=np.int64)
+    np.cumsum(L, out=offs[1:])
+    codes = np.concatenate(seqs).astype(np.uint8)
+    sd = np.zeros(n_seeds, dtype=inputs.SEED_DTYPE)
+    q = rng.integers(0, n_seqs, n_seeds)
+    t = np.where(rng.random(n_seeds) < 0.6, (q + half) % n_seqs,
+                 rng.integers(0, n_seqs, n_seeds))
+    k = np.minimum(np.minimum(L[q], L[t]), rng.integers(0, 18, n_seeds))
+    sd["q"], sd["t"], sd["k"] = q, t, k
+    sd["q_pos"] = (rng.random(n_seeds) * (L[q] - k + 1)).astype(np.int64)
+    sd["t_pos"] = (rng.random(n_seeds) * (L[t] - k + 1)).astype(np.int64)
+    shared = inputs.Batch(codes, offs, sd, alphabet)
+    unique = make_batch([(seqs[a], seqs[b], int(x), int(y), int(z))
+                         for a, b, x, y, z in zip(q, t, sd["q_pos"],
+                                                  sd["t_pos"], k)], alphabet)
+    return shared, unique
