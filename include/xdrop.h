@@ -109,11 +109,24 @@ enum {
                                     registers of the four waves) */
     XDROP_VARIANT_PLAIN = 3,     /* one wave per extension, one launch wave per
                                     extension, no queue: the baseline form */
-    XDROP_VARIANT_PAIR = 4       /* two extensions per wavefront (32-cell
+    XDROP_VARIANT_PAIR = 4,      /* two extensions per wavefront (32-cell
                                     windows, one cell per lane); extensions
                                     whose band outgrows 32 cells restart on
                                     the wave kernel.  Ignores band_cap (runs
                                     as WAVE when a cap is set) */
+    XDROP_VARIANT_DUAL16 = 5     /* two extensions per wavefront, one in each
+                                    16-bit half of every register (64-cell
+                                    windows, packed 16-bit integer
+                                    arithmetic on relative scores, paper
+                                    Sec. 4.1.4's change of ALU type); used
+                                    only where X + 40 * (max |entry| +
+                                    2 |gap|) <= 30,000 keeps every relative
+                                    score within 16 bits, else it runs as
+                                    WAVE (int32).  Extensions whose band
+                                    fills 60 lanes restart on the wave
+                                    kernel.  Ignores band_cap (runs as WAVE
+                                    when a cap is set).  Results are
+                                    bit-exact as on every form */
 };
 typedef struct {
     int32_t variant;      /* XDROP_VARIANT_* */
@@ -254,7 +267,8 @@ int xdrop_last_timing(xdrop_ctx *ctx, float *ms, int32_t n,
  * counts of extensions finished at each tile width: counts[0..3] = 1, 2, 4,
  * 8 cells per lane (wave kernel), counts[4] = pair kernel, counts[5] =
  * workgroup (block) tier, bands of 513..2,048 cells, counts[6] =
- * device-memory tier, wider bands. */
+ * device-memory tier, wider bands, counts[7] = two-extension 16-bit
+ * kernel. */
 int xdrop_last_stats(xdrop_ctx *ctx, int64_t *counts, int32_t n_counts);
 
 /* ---------------------------------------------------------------- serving

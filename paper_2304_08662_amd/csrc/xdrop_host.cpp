@@ -60,10 +60,12 @@ struct xdrop_ctx {
   int32_t* gen_scratch = nullptr;
   int gen_slots = 32;
   int32_t* last_counters = nullptr;  // counters of the last batch
+  int32_t last_combine_blocks = 0;    // its combine blocks (tier counts)
   char* scratch = nullptr;  // the device's fixed scratch (allocation-free
                             // entry point)
   int pair_blocks_per_cu[2] = {0, 0};
   int block_blocks_per_cu[2] = {0, 0};
+  int dual_blocks_per_cu[2] = {0, 0};
   int blocks_per_cu[2] = {0, 0};  // [alphabet]
   std::string arch;  // gfx name of the device (tuning cache key)
   std::vector<TunedEntry> tuned;  // xdrop_autotune / xdrop_load_tuning
@@ -79,7 +81,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 
-size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+constexpr size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
   size_t items, order, gen_q, dev_q, esc_q, bad, total;
@@ -166,7 +168,8 @@ int fill_scoring(const xdrop_scoring* sc, Params& P) {
 
 int check_options(const xdrop_options* o) {
   if (!o) return XDROP_OK;
-  if (o->variant < 0 || o->variant > XDROP_VARIANT_PAIR) return XDROP_E_INVALID;
+  if (o->variant < 0 || o->variant > XDROP_VARIANT_DUAL16)
+    return XDROP_E_INVALID;
   const int t = o->tile;
   if (!(t == 0 || t == 1 || t == 2 || t == 4 || t == 8))
     return XDROP_E_INVALID;
@@ -204,7 +207,8 @@ xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
   }
   // the pair kernel keeps no per-antidiagonal band width: a band cap runs on
   // the wave kernel
-  if (r.variant == XDROP_VARIANT_PAIR && r.band_cap > 0)
+  if ((r.variant == XDROP_VARIANT_PAIR || r.variant == XDROP_VARIANT_DUAL16) &&
+      r.band_cap > 0)
     r.variant = XDROP_VARIANT_WAVE;
   if (!r.tile) r.tile = 1;
   return r;
@@ -286,6 +290,9 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   if (!d_seqs || !d_offsets || !d_seeds || !d_results || n_seqs == 0)
     return XDROP_E_INVALID;
   xdrop_options o = resolve(c, sc, opts, n_seeds);
+  // the 16-bit kernel only where its relative scores are exact
+  if (o.variant == XDROP_VARIANT_DUAL16 && !dual_exact(P))
+    o.variant = XDROP_VARIANT_WAVE;
   const int32_t n_items = 2 * n_seeds;
   Layout L = layout(n_items, n_seqs);
   Workspace W;
@@ -299,6 +306,7 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
   }
   char* ws = W.ws;
   c->last_counters = W.counters;
+  c->last_combine_blocks = combine_blocks(n_seeds);
 
   P.seqs = (const uint32_t*)d_seqs;
   P.offsets = d_offsets;
@@ -359,6 +367,18 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     HIP_OK(launch_fill_queue(P.order, n_items, P.gen_queue, W.counters,
                              C_GEN_TAIL, st));
     if (timed) HIP_OK(hipEventRecord(ev[2], st));
+    if (timed) HIP_OK(hipEventRecord(ev[3], st));
+  } else if (o.variant == XDROP_VARIANT_DUAL16) {
+    // two extensions per wave in 16-bit halves; bands that fill a half's
+    // window are handed on to the wave kernel
+    const int pairs = (n_items + 1) / 2;
+    const int dgrid = std::min(c->num_cu * c->dual_blocks_per_cu[a],
+                               (pairs + WPB - 1) / WPB);
+    HIP_OK(launch_dual(P, dgrid, st));
+    if (timed) HIP_OK(hipEventRecord(ev[2], st));
+    Params Q = P;
+    Q.flags |= F_ESC;
+    HIP_OK(launch_wave(Q, persistent_grid(), st));
     if (timed) HIP_OK(hipEventRecord(ev[3], st));
   } else if (o.variant == XDROP_VARIANT_PAIR) {
     // two extensions per wave; bands wider than 32 cells are handed on to
@@ -451,6 +471,7 @@ int xdrop_ctx_create(int device, const xdrop_ctx_opts* opts,
     c->blocks_per_cu[a] = wave_blocks_per_cu(a);
     c->pair_blocks_per_cu[a] = pair_blocks_per_cu(a);
     c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
+    c->dual_blocks_per_cu[a] = dual_blocks_per_cu(a);
   }
   // the address of this device's fixed scratch, for the allocation-free
   // entry point
@@ -504,7 +525,7 @@ int xdrop_extend_batch_noalloc(xdrop_ctx* c, const uint8_t* d_seqs,
   if (n_seeds > XDROP_NOALLOC_MAX_SEEDS || n_seqs > XDROP_NOALLOC_MAX_SEQS)
     return XDROP_E_SCRATCH;
   // scratch: counters | device-memory tier rings | Layout regions
-  constexpr size_t CNT = 4096;
+  constexpr size_t CNT = align_up(C_COUNT * sizeof(int32_t));
   constexpr int SLOTS = 4;
   constexpr size_t RINGS = (size_t)SLOTS * 3 * GEN_CAP * sizeof(int32_t);
   const Layout L = layout(2 * n_seeds, n_seqs);
@@ -544,14 +565,19 @@ int xdrop_last_timing(xdrop_ctx* c, float* ms, int32_t n,
 
 int xdrop_last_stats(xdrop_ctx* c, int64_t* counts, int32_t n_counts) {
   if (!c || !counts || n_counts < 0) return XDROP_E_INVALID;
-  int32_t h[C_COUNT] = {0};
-  if (c->last_counters) {
-    if (hipMemcpy(h, c->last_counters, sizeof(h), hipMemcpyDeviceToHost) !=
-        hipSuccess)
-      return fail(c, hipErrorUnknown);
+  std::vector<int32_t> h((size_t)N_TIERS * MAX_COMBINE_BLOCKS, 0);
+  const int nb = c->last_counters ? c->last_combine_blocks : 0;
+  if (nb > 0 &&
+      hipMemcpy(h.data(), c->last_counters + C_PART,
+                (size_t)N_TIERS * nb * sizeof(int32_t),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, hipErrorUnknown);
+  for (int i = 0; i < n_counts; ++i) {
+    int64_t sum = 0;
+    if (i < N_TIERS)
+      for (int b = 0; b < nb; ++b) sum += h[(size_t)N_TIERS * b + i];
+    counts[i] = sum;
   }
-  for (int i = 0; i < n_counts; ++i)
-    counts[i] = i < N_TIERS ? h[C_REPORT + i] : 0;
   return XDROP_OK;
 }
 
@@ -745,6 +771,12 @@ extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
     o.variant = XDROP_VARIANT_WORKGROUP; o.tile = 1; o.chunk = 1;
     cand.push_back(o);
   }
+  if (dual_exact(tmp))
+    for (int ch : {1, 8}) {
+      xdrop_options o{};
+      o.variant = XDROP_VARIANT_DUAL16; o.tile = 1; o.chunk = ch;
+      cand.push_back(o);
+    }
   double mean_len = 0;
   rc = mean_extension_length(d_offsets, n_seqs, d_seeds, n_seeds, &mean_len);
   if (rc != XDROP_OK) return fail(c, hipErrorUnknown);
@@ -861,6 +893,8 @@ extern "C" int xdrop_resolve_options(xdrop_ctx* c, const xdrop_scoring* sc,
   rc = check_options(opts);
   if (rc != XDROP_OK) return rc;
   xdrop_options o = resolve(c, sc, opts, n_seeds);
+  if (o.variant == XDROP_VARIANT_DUAL16 && !dual_exact(tmp))
+    o.variant = XDROP_VARIANT_WAVE;
   finalize(c, sc->alphabet == XDROP_BYTE ? 1 : 0, 2 * n_seeds, o);
   *out = o;
   return XDROP_OK;

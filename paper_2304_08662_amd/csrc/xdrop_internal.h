@@ -29,6 +29,8 @@ constexpr int GEN_CAP = 1 << 16;      // device-memory tier band capacity
 struct ItemResult {
   int32_t best, x, y, status;
   int64_t cells;
+  int32_t tier;  // tier that finished the extension (C_TIER0 order), or -1
+  int32_t pad;
 };
 
 // Kernel flags.
@@ -75,6 +77,19 @@ struct Params {
   int16_t table[TABLE_DIM * TABLE_DIM];  // BYTE: sim - 2 gap, row = query
 };
 
+// Extensions finished per tier, in this order: 1, 2, 4, 8 cells per lane
+// (wave kernel), pair kernel, block tier, device-memory tier, two-extension
+// 16-bit kernel.  Each result records its tier; the combine kernel counts
+// them per block (no device-wide atomic per extension).
+constexpr int N_TIERS = 8;
+// Combine blocks of a batch (at most, so that the per-block tier counts fit
+// in the counter block).
+constexpr int MAX_COMBINE_BLOCKS = 2048;
+inline int combine_blocks(int n_seeds) {
+  const int b = (n_seeds + 255) / 256;
+  return b < 1 ? 1 : b > MAX_COMBINE_BLOCKS ? MAX_COMBINE_BLOCKS : b;
+}
+
 // Counter layout (int32 slots).
 enum {
   C_HEAD = 0,       // main queue head
@@ -85,15 +100,14 @@ enum {
   C_PAIR_HEAD = 5,  // pair kernel queue head
   C_DEV_TAIL = 6,   // device-memory tier queue tail
   C_DEV_HEAD = 7,   // its head
-  C_TIER0 = 8,      // extensions finished per tier: 1,2,4,8 cells per lane,
-                    // pair, block, device memory
-  C_HIST = 16,      // longest-first ordering: bucket sizes
+  C_HIST = 8,       // longest-first ordering: bucket sizes
   C_CURSOR = C_HIST + 256,  // bucket write cursors
-  C_REPORT = C_CURSOR + 256,  // the finished batch's tier counts (7)
-  C_COUNT = C_REPORT + 8
+  // the last batch's tier counts, N_TIERS per combine block (block b at
+  // C_PART + N_TIERS * b); the host sums them when asked
+  C_PART = C_CURSOR + 256,
+  C_COUNT = C_PART + N_TIERS * MAX_COMBINE_BLOCKS
 };
 constexpr int NBUCKET = 256;
-constexpr int N_TIERS = 7;
 
 }  // namespace xd
 
@@ -117,6 +131,9 @@ hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
 hipError_t launch_wave(const Params& P, int grid, hipStream_t s);
 hipError_t launch_pair(const Params& P, int grid, hipStream_t s);
 int pair_blocks_per_cu(int alphabet);
+hipError_t launch_dual(const Params& P, int grid, hipStream_t s);
+int dual_blocks_per_cu(int alphabet);
+bool dual_exact(const Params& P);  // 16-bit relative scores exact here
 hipError_t launch_block(const Params& P, int grid, hipStream_t s);
 int block_blocks_per_cu(int alphabet);
 hipError_t launch_general(const Params& P, int grid, hipStream_t s);

@@ -242,6 +242,10 @@ struct RingT<1, RS_, NT> {  // one byte per code
       v0 = __builtin_bswap32(hi);
       v1 = __builtin_bswap32(lo);
     }
+    // (codes above 31 are invalid input, reported by the symbol check; kept
+    // below 32 here so that every score-table index stays in its row)
+    v0 &= 0x1F1F1F1Fu;
+    v1 &= 0x1F1F1F1Fu;
     int wi = ((c0 >> 2) + 2 * l) & (RW - 1);
     ring[wi] = v0;
     ring[wi + 1] = v1;
@@ -649,24 +653,24 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   const int lane = lane_id();
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
   // DNA: the query code of each lane copied into all 16 code slots of a
-  // word; bytes: 32 x the query code (a table row) and the target code
+  // word; bytes: the byte offset of the lane's row of the score table (row
+  // = query code, 32 entries of 4 bytes)
   uint32_t fa = 0;
-  int fb = 0;
   auto load_fa = [&]() {
     if constexpr (ALPHA == 0) {
       fa = (Ring<0>::read(w.ra, base + lane - 1) & 3u) * 0x55555555u;
     } else {
       uint32_t t[1];
       Ring<1>::read<1>(w.ra, base + lane - 1, t);
-      fa = (t[0] & 31u) << 5;
+      fa = (t[0] & 31u) << 7;
     }
   };
+  // bytes: score of the lane's cell for target code c
+  auto score = [&](uint32_t c) {
+    return *reinterpret_cast<const int*>(
+        reinterpret_cast<const char*>(tab) + fa + (c << 2));
+  };
   load_fa();
-  if constexpr (ALPHA == 1) {
-    uint32_t t[1];
-    Ring<1>::read<1>(w.rb, d0 - base - lane - 1, t);
-    fb = (int)(t[0] & 31u);
-  }
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
   uint32_t acc = 0;         // sum over d of (65 - live-span cells)
@@ -675,6 +679,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // tv, which is T in the frame of the next antidiagonal
   int bd = -1, bxa = 0, bln = 0;
   int pm = 0, mrel = 0;     // d - n - base, m - base (edge clamps and masks)
+  uint64_t in_m = 0;        // edge blocks: the lanes with x <= m
   int rem = 0;              // edge blocks: d_end - d
   // antidiagonals per block (the block's fixed work spreads over 32
   // steps): DNA reads two match words, bytes 32 target codes into qw
@@ -687,7 +692,14 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
   // the two antidiagonals before the block, lane k + 2 the block's k-th
   int ml = 0, mh = 0;
-  uint32_t qw[8] = {};  // bytes: codes entering lane 0
+  // bytes: the ring position of the lane's target code on the block's first
+  // antidiagonal (cell base + l of antidiagonal d + k takes b[d + k - base -
+  // l - 1], k bytes further on: an immediate offset of the read); the score
+  // of the next antidiagonal and the codes of the two after it are read
+  // ahead of their use
+  const uint8_t* cp = reinterpret_cast<const uint8_t*>(w.rb);
+  int sc_next = 0;
+  uint32_t cd1 = 0, cd2 = 0;
 
   // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
   // finite-lane masks mp and mpp; pp and mpp receive d + k (the two
@@ -709,7 +721,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       sim = (t & vmat) | (~t & vmis);
       opaque_v(sim);  // (the select stays whole, so the add below is VOP2)
     } else {
-      sim = tab[(int)fa + fb];
+      sim = sc_next;
+      sc_next = score(cd1);
+      cd1 = cd2;
+      cd2 = cp[k + 3];
     }
     // (every lane of a wave rotation has a source, so bound_ctrl changes
     // nothing; it lets the compiler fold the move into its user, a VOP2
@@ -721,8 +736,8 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     opaque_v(uh);
     const int v = max(uh, dg + sim);
     uint64_t fm = ballot(v >= thr);
-    if constexpr (EDGE)  // y > n below pm, x > m above mrel
-      fm &= ballot((uint32_t)(lane - (pm + k)) <= (uint32_t)(mrel - (pm + k)));
+    if constexpr (EDGE)  // y > n below pm + k, x > m above mrel (block mask)
+      fm &= ballot(lane >= pm + k) & in_m;
     const int vn = __builtin_amdgcn_inverse_ballot_w64(fm) ? v : NEG;
     // away from the edges a cell with v > tv >= thr is finite, so the
     // improvement test need not wait for the select
@@ -753,11 +768,6 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     ml = xd_writelane_i32((int)(uint32_t)fm, k + 2, ml);
     mh = xd_writelane_i32((int)(uint32_t)(fm >> 32), k + 2, mh);
     tv -= gap;
-    if constexpr (ALPHA == 1) {
-      // the target codes move one cell up; lane 0 takes the next one
-      const int in = (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
-      fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
-    }
     if ((k & (G - 1)) == G - 1) {
       const uint64_t o = mp | fm;
       if ((k & 3) == 3 && o == 0) return true;
@@ -786,13 +796,6 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       const bool in = src < 64;
       const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
       const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y);
-      if constexpr (ALPHA == 1) {
-        // target codes move with their cells; the top lanes receive stray
-        // codes, which no finite cell uses before they have moved out (a
-        // cell there has a -infinity diagonal predecessor until the band
-        // reaches it)
-        fb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb);
-      }
       x = in ? pn : NEG;
       y = in ? po : NEG;
       m1 >>= sl;
@@ -805,6 +808,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     pm = d - n - base;
     mrel = m - base;
     rem = d_end - d;
+    in_m = ballot(lane <= mrel);
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + KB - 1);
     if constexpr (ALPHA == 0) {
@@ -815,9 +819,13 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
         mw[h] = ~(xw | (xw >> 1)) & 0x55555555u;
       }
     } else {
-      Ring<1>::read<8>(w.rb, e0, qw);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) qw[i] = (uint32_t)in_vgpr((int)qw[i]);
+      // (reads up to 34 bytes past a position of the ring, which its mirror
+      // words cover; codes past those covered belong to no block step)
+      cp = reinterpret_cast<const uint8_t*>(w.rb) +
+           ((e0 - lane - 1) & (Ring<1>::RS - 1));
+      sc_next = score(cp[0]);
+      cd1 = cp[1];
+      cd2 = cp[2];
     }
     ml = xd_writelane_i32((int)(uint32_t)m2, 0, ml);
     mh = xd_writelane_i32((int)(uint32_t)(m2 >> 32), 0, mh);
@@ -1339,7 +1347,8 @@ __device__ __forceinline__ ItemSetup setup_item(const Params& P, int item) {
 
 __device__ __forceinline__ int tier_index(int C) {
   return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : C == 8 ? 3 : 4;
-}  // the block tier counts at index 5, the device-memory tier at 6
+}  // the block tier counts at index 5, the device-memory tier at 6, the
+   // two-extension 16-bit kernel at 7
 
 template <int ALPHA, int CMIN, int CMAX>
 __device__ __forceinline__ void run_item(const Params& P, const Src& S, int item,
@@ -1347,6 +1356,7 @@ __device__ __forceinline__ void run_item(const Params& P, const Src& S, int item
   ItemSetup s = setup_item(P, item);
   ItemResult res;
   res.best = 0; res.x = 0; res.y = 0; res.status = s.status; res.cells = 0;
+  res.tier = -1; res.pad = 0;
   bool handed_on = false;
   if (s.status == S_OK) {
     Ext& e = s.e;
@@ -1367,8 +1377,7 @@ __device__ __forceinline__ void run_item(const Params& P, const Src& S, int item
       res.status = S_BAND;
     } else {
       res.best = e.T; res.x = e.bx; res.y = e.by; res.cells = e.W;
-      if (lane_id() == 0)
-        atomicAdd(P.counters + C_TIER0 + tier_index(tier), 1);
+      res.tier = tier_index(tier);
     }
   }
   if (!handed_on && lane_id() == 0) P.items[item] = res;
@@ -1376,9 +1385,12 @@ __device__ __forceinline__ void run_item(const Params& P, const Src& S, int item
 
 // Persistent wave kernel: extensions of the batch pulled from the queue in
 // chunks of P.chunk (or, in the plain form, one per launched wave), tiles of
-// 1..CMAX cells per lane.
+// 1..CMAX cells per lane.  Occupancy target six waves per SIMD: the compiler
+// then keeps the kernel within 80 registers per lane, and the one-cell loop,
+// bound by vector issue with dependent steps, gains from the sixth wave.
 template <int ALPHA, int CMAX>
-__global__ __launch_bounds__(WAVE * WPB) void xd_wave_kernel(Params P) {
+__global__ __launch_bounds__(WAVE * WPB) __attribute__((amdgpu_waves_per_eu(6)))
+void xd_wave_kernel(Params P) {
   constexpr int CMIN = 1;
   __shared__ WaveLds<ALPHA> lds[WPB];
   __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
@@ -1504,10 +1516,8 @@ __device__ __forceinline__ void run_pair(const Params& P, const Src& S,
       ItemResult r;
       r.best = 0; r.x = 0; r.y = 0; r.status = st.status;
       r.cells = st.status == S_OK ? 1 : 0;
-      if (lane == 0) {
-        P.items[items[h]] = r;
-        if (st.status == S_OK) atomicAdd(P.counters + C_TIER0 + 4, 1);
-      }
+      r.tier = st.status == S_OK ? 4 : -1; r.pad = 0;
+      if (lane == 0) P.items[items[h]] = r;
       continue;
     }
     H[h].own = 1;
@@ -1736,6 +1746,7 @@ __device__ __forceinline__ void run_pair(const Params& P, const Src& S,
     ItemResult r;
     r.status = S_OK;
     r.cells = H[h].e.W;
+    r.tier = 4; r.pad = 0;
     if (H[h].bd >= 0) {
       r.best = H[h].tbest + gap * H[h].bd;
       r.x = H[h].bxa;
@@ -1743,10 +1754,7 @@ __device__ __forceinline__ void run_pair(const Params& P, const Src& S,
     } else {
       r.best = 0; r.x = 0; r.y = 0;
     }
-    if (lane == 0) {
-      P.items[H[h].item] = r;
-      atomicAdd(P.counters + C_TIER0 + 4, 1);
-    }
+    if (lane == 0) P.items[H[h].item] = r;
   }
 }
 
@@ -1764,17 +1772,497 @@ __global__ __launch_bounds__(WAVE * WPB) void xd_pair_kernel(Params P) {
   const int wid = threadIdx.x >> 6;
   PairLds<ALPHA>& L = lds[wid];
   const Src S = make_src(P);
+  // pairs of consecutive slots, claimed P.chunk pairs at a time (one device
+  // atomic per claim)
+  int cur = 0, end = 0;
   for (;;) {
-    int c = 0;
-    if (lane_id() == 0) c = atomicAdd(P.counters + C_PAIR_HEAD, 2);
-    c = uni(c);
-    if (c >= P.n_items) break;
+    if (cur >= end) {
+      int c = 0;
+      if (lane_id() == 0) c = atomicAdd(P.counters + C_PAIR_HEAD, 2 * P.chunk);
+      cur = uni(c);
+      end = min(cur + 2 * P.chunk, P.n_items);
+      if (cur >= P.n_items) break;
+    }
+    const int c = cur;
+    cur += 2;
     const int i0 = (P.flags & F_ORDERED) ? uni(P.order[c]) : c;
     int i1 = -1;
-    if (c + 1 < P.n_items)
+    if (c + 1 < end)
       i1 = (P.flags & F_ORDERED) ? uni(P.order[c + 1]) : c + 1;
     run_pair<ALPHA>(P, S, i0, i1, L, tab);
   }
+}
+
+// ------------------------------------------------------------------ dual16
+// Two extensions per wavefront in the two 16-bit halves of every register
+// (the paper changed the ALU type of its inner loop for dual issue, Sec.
+// 4.1.4; here packed 16-bit integer operations do the work of two
+// extensions at once): lane l holds window position l of extension 0 in the
+// low half and of extension 1 in the high half, one cell per lane each, and
+// one v_pk_max_i16 / v_pk_add_i16 advances both.  Scores are kept relative:
+// a register half holds V - off_h (V = S - gap*d, as in the wave kernel),
+// and after every block of antidiagonals each half is rebased so that its
+// best score sits at 0; every finite value then stays within
+// [-X - 3*max_abs, 33*max_abs], which the host checks fits 16 bits (else
+// the batch runs on the int32 wave kernel).  -infinity is -32768 and the
+// adds saturate, so it stays below every threshold.  Each half runs its own
+// extension at its own antidiagonal and window; when one ends, that half
+// takes the next extension from the queue while the other goes on.  The
+// band bookkeeping follows the one-cell loop of the wave kernel (finite-lane
+// ballots, four guard lanes at the window top, the window sliding up in
+// place); a band that fills the window is handed on to the wave kernel,
+// which restarts the extension.
+typedef short xd_short2 __attribute__((ext_vector_type(2)));
+typedef unsigned short xd_ushort2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_add_sat(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(
+      uint32_t, __builtin_elementwise_add_sat(__builtin_bit_cast(xd_short2, a),
+                                              __builtin_bit_cast(xd_short2, b)));
+}
+__device__ __forceinline__ uint32_t pk_sub_sat(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(
+      uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(xd_short2, a),
+                                              __builtin_bit_cast(xd_short2, b)));
+}
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(
+      uint32_t, __builtin_elementwise_max(__builtin_bit_cast(xd_short2, a),
+                                          __builtin_bit_cast(xd_short2, b)));
+}
+__device__ __forceinline__ uint32_t pack16(int lo, int hi) {
+  return ((uint32_t)lo & 0xFFFFu) | ((uint32_t)hi << 16);
+}
+__device__ __forceinline__ int half16(uint32_t v, int h) {
+  return h ? (int)(short)(v >> 16) : (int)(short)v;
+}
+
+constexpr int NEG16 = -32768;
+constexpr uint32_t NEG2 = 0x80008000u;
+// the host runs a batch here only if X + DUAL_SPAN * max_abs fits 16 bits
+constexpr int DUAL_SPAN = 40;
+
+template <int ALPHA>
+struct DualLds {
+  WaveLds<ALPHA> h[2];
+};
+
+// Uniform state of one half's extension.
+struct DualHalf {
+  Ext e;        // lengths, sources, ring levels, d, base (other fields unused)
+  int item;     // -1: none
+  int off;      // register half = V - off
+  int tv;       // T in the frame of antidiagonal e.d, relative (V - off)
+  int bd, bln;  // last new best: antidiagonal and lane (bd < 0: none yet)
+  int bxa;      // its x
+  uint64_t m1, m2;  // finite lanes of e.d - 1 and e.d - 2
+};
+
+// Starts `item` in half h (registers x: antidiagonal 0, y: antidiagonal -1).
+// Returns false (result written, half left idle) for an extension that
+// needs no sweep or has a bad seed.
+template <int ALPHA>
+__device__ __forceinline__ bool dual_start(const Params& P, const Src& S,
+                                           int item, int h, DualHalf& H,
+                                           WaveLds<ALPHA>& w, uint32_t& x,
+                                           uint32_t& y, uint32_t& fa2,
+                                           uint32_t& fb2) {
+  const int lane = lane_id();
+  ItemSetup st = setup_item(P, item);
+  if (st.status != S_OK || st.e.m + st.e.n == 0) {
+    ItemResult r;
+    r.best = 0; r.x = 0; r.y = 0; r.status = st.status;
+    r.cells = st.status == S_OK ? 1 : 0;
+    r.tier = st.status == S_OK ? 7 : -1; r.pad = 0;
+    if (lane == 0) P.items[item] = r;
+    return false;
+  }
+  H.e = st.e;
+  H.item = item;
+  H.off = 0;
+  H.tv = -P.gap;  // T = 0 in the frame of antidiagonal 1
+  H.bd = -1; H.bln = 0; H.bxa = 0;
+  H.m1 = 1;  // antidiagonal 0: S(0,0) = 0 at lane 0
+  H.m2 = 0;
+  const uint32_t hm = h ? 0xFFFF0000u : 0x0000FFFFu;
+  x = (x & ~hm) | ((lane == 0 ? 0u : NEG2) & hm);
+  y = (y & ~hm) | (NEG2 & hm);
+  cover_a<ALPHA>(H.e, w, S, 62);
+  cover_b<ALPHA>(H.e, w, S, 0);
+  if constexpr (ALPHA == 1) {
+    uint32_t t[1];
+    Ring<1>::read<1>(w.ra, lane - 1, t);
+    const uint32_t fa = (t[0] & 31u) << 6;  // byte offset of the table row
+    Ring<1>::read<1>(w.rb, -lane, t);       // b[d - base - lane - 1], d = 1
+    const uint32_t fb = (t[0] & 31u) << 1;
+    fa2 = (fa2 & ~hm) | ((fa << (16 * h)) & hm);
+    fb2 = (fb2 & ~hm) | ((fb << (16 * h)) & hm);
+  } else {
+    const uint32_t fa = (Ring<0>::read(w.ra, lane - 1) & 3u) * 0x55555555u;
+    fa2 = h ? fa2 : fa;  // (DNA: query codes of half h kept in fa2 / fb2)
+    fb2 = h ? fa : fb2;
+  }
+  return true;
+}
+
+template <int ALPHA>
+__device__ __forceinline__ void run_dual(const Params& P, const Src& S,
+                                         DualLds<ALPHA>& L,
+                                         const int16_t* tab16) {
+  const int lane = lane_id();
+  const int gap = P.gap, X = P.X;
+  DualHalf H[2];
+  H[0].item = H[1].item = -1;
+  uint32_t x = NEG2, y = NEG2;  // x: antidiagonal d-1, y: d-2 (both halves)
+  uint32_t fa2 = 0, fb2 = 0;    // bytes: table row / column offsets;
+                                // DNA: query codes of half 0 / half 1
+  bool drained = false;
+  constexpr int KB = 32;        // antidiagonals per block
+  constexpr int G = 4;          // guard lanes at the window top
+  const uint32_t vmat2 = (uint32_t)in_vgpr((int)pack16(P.mat_s, P.mat_s));
+  const uint32_t vmis2 = (uint32_t)in_vgpr((int)pack16(P.mis_s, P.mis_s));
+  int cur = 0, end = 0;  // slots claimed from the queue, P.chunk at a time
+  for (;;) {
+    // idle halves take the next extensions
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      while (H[h].item < 0 && !drained) {
+        if (cur >= end) {
+          int c = 0;
+          if (lane == 0) c = atomicAdd(P.counters + C_HEAD, P.chunk);
+          cur = uni(c);
+          end = min(cur + P.chunk, P.n_items);
+          if (cur >= P.n_items) { drained = true; break; }
+        }
+        const int c = cur++;
+        const int item = (P.flags & F_ORDERED) ? uni(P.order[c]) : c;
+        dual_start<ALPHA>(P, S, item, h, H[h], L.h[h], x, y, fa2, fb2);
+      }
+    }
+    const bool live0 = H[0].item >= 0, live1 = H[1].item >= 0;
+    if (!live0 && !live1) break;
+    // ---- one block of antidiagonals for both halves
+    int pm[2], mrel[2], rem[2], d0[2];
+    bool edge = false;
+    uint32_t qw[2][8];   // bytes: codes entering lane 0, per half
+    uint32_t mw[2][2];   // DNA: match words per half
+    uint32_t mp2[4];     // DNA: steps 8i .. 8i + 7, half 0 low, half 1 high
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      DualHalf& Hh = H[h];
+      d0[h] = Hh.e.d;
+      if (Hh.item < 0) {
+        pm[h] = 0; mrel[h] = 63; rem[h] = KB;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) qw[h][i] = 0;
+        mw[h][0] = mw[h][1] = 0;
+        continue;
+      }
+      pm[h] = Hh.e.d - Hh.e.n - Hh.e.base;
+      mrel[h] = Hh.e.m - Hh.e.base;
+      rem[h] = Hh.e.m + Hh.e.n - Hh.e.d;  // antidiagonals left after d
+      if (!(pm[h] + KB - 1 <= 0 && mrel[h] >= 63 && rem[h] >= KB - 1))
+        edge = true;
+      const int e0 = Hh.e.d - Hh.e.base;
+      cover_b<ALPHA>(Hh.e, L.h[h], S, e0 + KB - 1);
+      if constexpr (ALPHA == 1) {
+        // codes doubled (byte offsets of table columns; codes < 32, so no
+        // byte carries into the next)
+        Ring<1>::read<8>(L.h[h].rb, e0, qw[h]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          qw[h][i] = (uint32_t)in_vgpr((int)((qw[h][i] & 0x1F1F1F1Fu) << 1));
+      } else {
+        const uint32_t fa = h ? fb2 : fa2;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const uint32_t xw =
+              Ring<0>::read(L.h[h].rb, e0 - lane - 1 + 16 * i) ^ fa;
+          mw[h][i] = ~(xw | (xw >> 1)) & 0x55555555u;
+        }
+      }
+    }
+    // an idle half (all -infinity) never passes its threshold and never
+    // improves: its T sits at the top of the 16-bit range
+    int tv0 = live0 ? H[0].tv : 0x7FFF, tv1 = live1 ? H[1].tv : 0x7FFF;
+    if constexpr (ALPHA == 0) {
+      // low 16 bits of half 0's word beside those of half 1's (steps 0-7 of
+      // the word), then the high 16 bits (steps 8-15)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        mp2[2 * i] = __builtin_amdgcn_perm(mw[1][i], mw[0][i], 0x05040100u);
+        mp2[2 * i + 1] = __builtin_amdgcn_perm(mw[1][i], mw[0][i], 0x07060302u);
+      }
+    }
+    uint64_t a1[2] = {H[0].m1, H[1].m1}, a2[2] = {H[0].m2, H[1].m2};
+    int bd[2] = {H[0].bd, H[1].bd}, bln[2] = {H[0].bln, H[1].bln};
+    // finite-lane masks of the block's antidiagonals for the live-span
+    // count, per half in lanes of two registers (low and high words): lanes
+    // 0 and 1 the two antidiagonals before the block, lane k + 2 the k-th
+    int ml[2] = {0, 0}, mh[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      ml[h] = xd_writelane_i32((int)(uint32_t)a2[h], 0, ml[h]);
+      mh[h] = xd_writelane_i32((int)(uint32_t)(a2[h] >> 32), 0, mh[h]);
+      ml[h] = xd_writelane_i32((int)(uint32_t)a1[h], 1, ml[h]);
+      mh[h] = xd_writelane_i32((int)(uint32_t)(a1[h] >> 32), 1, mh[h]);
+    }
+    const uint32_t xhi = ((uint32_t)X << 16) | 0xFFFFu;
+    int nk = KB;
+    bool newest_in_y = false;
+    // antidiagonal d_h + k of both halves: prev (d-1, masks mp), pp (d-2,
+    // masks mpp) -> pp, mpp.  True when a live half's band reached the guard
+    // lanes, or it had two dead antidiagonals (tested every G), or at its
+    // last antidiagonal (edge blocks).
+    auto body = [&](auto edge_tag, uint32_t& prev, uint32_t& pp,
+                    uint64_t (&mp)[2], uint64_t (&mpp)[2], int k) -> bool {
+      constexpr bool EDGE = decltype(edge_tag)::value;
+      const uint32_t thr2 = pack16(tv0 - X, tv1 - X);
+      uint32_t sim2;
+      if constexpr (ALPHA == 1) {
+        const uint32_t a2v = fa2 + fb2;  // (no carry between the halves)
+        const int s0 = tab16[(a2v & 0xFFFFu) >> 1];
+        const int s1 = tab16[a2v >> 17];
+        sim2 = pack16(s0, s1);
+      } else {
+        // match bit of both halves to bit 15 of each, then spread it over
+        // the half: 0xFFFF on a match
+        const uint32_t sh = (uint32_t)(15 - 2 * (k & 7));
+        int sel = (int)__builtin_bit_cast(
+            uint32_t, __builtin_bit_cast(xd_ushort2, mp2[k >> 3]) << (unsigned short)sh);
+        sel = (int)__builtin_bit_cast(
+            uint32_t, __builtin_bit_cast(xd_short2, (uint32_t)sel) >> (short)15);
+        opaque_v(sel);  // (one v_bfi below, not compares and selects)
+        sim2 = (vmat2 & (uint32_t)sel) | (vmis2 & ~(uint32_t)sel);
+      }
+      const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)prev, 0x13C, 0xf, 0xf, false);
+      const uint32_t dg = (uint32_t)__builtin_amdgcn_mov_dpp((int)pp, 0x13C, 0xf, 0xf, false);
+      const uint32_t v = pk_max(pk_max(up, prev), pk_add_sat(dg, sim2));
+      // per half v - thr: not negative exactly when the cell survives (and
+      // exact up to X + max_abs, far below the 16-bit limit)
+      const uint32_t r = pk_sub_sat(v, thr2);
+      uint64_t f0 = ballot((int)(short)r >= 0);
+      uint64_t f1 = ballot((int)r >= 0);
+      uint32_t vn;
+      if constexpr (EDGE) {
+        // cells outside the matrix: y > n below pm, x > m above mrel
+        f0 &= ballot((uint32_t)(lane - (pm[0] + k)) <= (uint32_t)(mrel[0] - (pm[0] + k)));
+        f1 &= ballot((uint32_t)(lane - (pm[1] + k)) <= (uint32_t)(mrel[1] - (pm[1] + k)));
+        const uint32_t keep =
+            (__builtin_amdgcn_inverse_ballot_w64(f0) ? 0x0000FFFFu : 0u) |
+            (__builtin_amdgcn_inverse_ballot_w64(f1) ? 0xFFFF0000u : 0u);
+        vn = (v & keep) | (NEG2 & ~keep);
+      } else {
+        int neg = (int)__builtin_bit_cast(
+            uint32_t, __builtin_bit_cast(xd_short2, r) >> (short)15);
+        opaque_v(neg);  // (one v_bfi, not compares and selects per half)
+        vn = (v & ~(uint32_t)neg) | (NEG2 & (uint32_t)neg);
+      }
+      // a new best: v > tv, i.e. v - thr > X
+      uint64_t i0 = ballot((int)(short)r > X);
+      uint64_t i1 = ballot((int)r > (int)xhi);  // (signed: high half > X)
+      if constexpr (EDGE) {
+        i0 &= f0;
+        i1 &= f1;
+      }
+      pp = vn;
+      if (__builtin_expect((i0 | i1) != 0, 0)) {
+        const uint64_t im[2] = {i0, i1};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (!im[h]) continue;
+          const int hv = half16(vn, h);
+          int l0 = __builtin_ctzll(im[h]);
+          int wm = __builtin_amdgcn_readlane(hv, l0);
+          if (__builtin_popcountll(im[h]) > 1) {
+            wm = uni(wave_max(hv));
+            l0 = __builtin_ctzll(ballot(hv == wm));
+          }
+          if (h) tv1 = wm; else tv0 = wm;
+          bd[h] = d0[h] + k;
+          bln[h] = l0;
+        }
+      }
+      mpp[0] = f0;
+      mpp[1] = f1;
+      ml[0] = xd_writelane_i32((int)(uint32_t)f0, k + 2, ml[0]);
+      mh[0] = xd_writelane_i32((int)(uint32_t)(f0 >> 32), k + 2, mh[0]);
+      ml[1] = xd_writelane_i32((int)(uint32_t)f1, k + 2, ml[1]);
+      mh[1] = xd_writelane_i32((int)(uint32_t)(f1 >> 32), k + 2, mh[1]);
+      tv0 -= gap;
+      tv1 -= gap;
+      if constexpr (ALPHA == 1) {
+        // byte k&3 of half 0's word to byte 0, of half 1's to byte 2, zeros
+        // elsewhere (v_perm_b32 selector 0x0c gives a zero byte)
+        const uint32_t in2 = __builtin_amdgcn_perm(
+            qw[1][k >> 2], qw[0][k >> 2],
+            (uint32_t)(k & 3) | 0x0C000000u | ((uint32_t)(4 + (k & 3)) << 16) |
+                0x0C00u);
+        fb2 = (uint32_t)__builtin_amdgcn_update_dpp((int)in2, (int)fb2, 0x138,
+                                                   0xf, 0xf, false);
+      }
+      bool stop = false;
+      if ((k & (G - 1)) == G - 1) {
+        const uint64_t o0 = mp[0] | f0, o1 = mp[1] | f1;
+        if ((live0 && o0 == 0) || (live1 && o1 == 0)) stop = true;
+        // one of the top G lanes finite (an idle half has none)
+        uint32_t hw = (uint32_t)((o0 | o1) >> 32);
+        opaque_s(hw);
+        if (hw >= (1u << (32 - G))) stop = true;
+      }
+      if constexpr (EDGE) {
+        if ((live0 && k >= rem[0]) || (live1 && k >= rem[1])) stop = true;
+      }
+      return stop;
+    };
+    auto run_block = [&](auto edge_tag) {
+#pragma unroll
+      for (int k = 0; k < KB; k += 2) {
+        if (body(edge_tag, x, y, a1, a2, k)) {
+          nk = k + 1; newest_in_y = true; return;
+        }
+        if (body(edge_tag, y, x, a2, a1, k + 1)) { nk = k + 2; return; }
+      }
+    };
+    if (edge) run_block(std::true_type{});
+    else run_block(std::false_type{});
+    if (newest_in_y) {
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+    // live-span cells of the block's antidiagonals per half: lane k + 2
+    // forms antidiagonal k's span from the masks of the two before it (lanes
+    // k + 1 and k), clamped to the matrix
+    int64_t acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t al = (uint32_t)wave_shr1(ml[h], 0), ah = (uint32_t)wave_shr1(mh[h], 0);
+      const uint32_t bl = (uint32_t)wave_shr1((int)al, 0), bh = (uint32_t)wave_shr1((int)ah, 0);
+      const uint32_t cl = al | (bl << 1);
+      const uint32_t ch = ah | __builtin_amdgcn_alignbit(bh, bl, 31);
+      const uint32_t cz = min((uint32_t)__builtin_ctzg(cl, -1),
+                              (uint32_t)__builtin_ctzg(ch, -1) | 32u);
+      const uint32_t lz = min((uint32_t)__builtin_clzg(ah | bh, -1),
+                              (uint32_t)__builtin_clzg(al | bl, -1) | 32u);
+      const int kk = lane - 2;
+      const int lo = max((int)cz, pm[h] + kk);
+      const int hi = min(64 - (int)lz, mrel[h]);
+      const bool live = (al | ah | bl | bh) != 0;
+      const int cnt = (kk >= 0 && kk < nk && live) ? max(hi - lo + 1, 0) : 0;
+      acc[h] = sum_lanes(cnt);
+    }
+    // ---- after the block: advance, rebase, and see to each half
+    const int tvs[2] = {tv0, tv1};
+    uint32_t delta2 = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      DualHalf& Hh = H[h];
+      if (Hh.item < 0) continue;
+      Hh.e.d += nk;
+      Hh.e.W += acc[h];
+      if (bd[h] >= d0[h]) Hh.bxa = Hh.e.base + bln[h];  // a new best here
+      Hh.bd = bd[h];
+      Hh.bln = bln[h];
+      // rebase: the half's best score at 0
+      Hh.off += tvs[h];
+      Hh.tv = 0;
+      delta2 |= ((uint32_t)tvs[h] & 0xFFFFu) << (16 * h);
+    }
+    x = pk_sub_sat(x, delta2);
+    y = pk_sub_sat(y, delta2);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      DualHalf& Hh = H[h];
+      if (Hh.item < 0) continue;
+      const uint32_t hm = h ? 0xFFFF0000u : 0x0000FFFFu;
+      Hh.m1 = ballot(half16(x, h) != NEG16);
+      Hh.m2 = ballot(half16(y, h) != NEG16);
+      const bool dead = (Hh.m1 | Hh.m2) == 0;
+      const bool last = Hh.e.d > Hh.e.m + Hh.e.n;
+      if (dead || last) {
+        // finished: T in the S frame from the relative frame value
+        ItemResult r;
+        r.status = S_OK;
+        r.cells = Hh.e.W;
+        r.tier = 7; r.pad = 0;
+        if (Hh.bd >= 0) {
+          r.best = Hh.off + gap * Hh.e.d;  // (tv = 0 after the rebase)
+          r.x = Hh.bxa;
+          r.y = Hh.bd - Hh.bxa;
+        } else {
+          r.best = 0; r.x = 0; r.y = 0;
+        }
+        if (lane == 0) P.items[Hh.item] = r;
+        Hh.item = -1;
+        x = (x & ~hm) | (NEG2 & hm);
+        y = (y & ~hm) | (NEG2 & hm);
+        continue;
+      }
+      const uint64_t o = Hh.m1 | Hh.m2;
+      const int cz = (int)__builtin_clzll(o);
+      if (cz < G) {
+        // the band reached the guard lanes: slide the half's window up by
+        // the lanes below its lowest finite cell, or hand the extension on
+        const int sl = (int)__builtin_ctzll(o);
+        if (cz + sl < G) {
+          if (lane == 0) {
+            const int slot = atomicAdd(P.counters + C_ESC_TAIL, 1);
+            P.esc_queue[slot] = Hh.item;
+          }
+          Hh.item = -1;
+          x = (x & ~hm) | (NEG2 & hm);
+          y = (y & ~hm) | (NEG2 & hm);
+          continue;
+        }
+        const int src = lane + sl;
+        const bool in = src < 64;
+        const uint32_t px = (uint32_t)__builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)x);
+        const uint32_t py = (uint32_t)__builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)y);
+        x = (x & ~hm) | ((in ? px : NEG2) & hm);
+        y = (y & ~hm) | ((in ? py : NEG2) & hm);
+        if constexpr (ALPHA == 1) {
+          // target codes move with their cells (stray codes at the top lanes
+          // are not used before they have moved out)
+          const uint32_t pb = (uint32_t)__builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)fb2);
+          fb2 = (fb2 & ~hm) | (pb & hm);
+        }
+        Hh.m1 >>= sl;
+        Hh.m2 >>= sl;
+        Hh.e.base += sl;
+        cover_a<ALPHA>(Hh.e, L.h[h], S, Hh.e.base + 62);
+        if constexpr (ALPHA == 1) {
+          uint32_t t[1];
+          Ring<1>::read<1>(L.h[h].ra, Hh.e.base + lane - 1, t);
+          const uint32_t fa = (t[0] & 31u) << 6;
+          fa2 = (fa2 & ~hm) | ((fa << (16 * h)) & hm);
+        } else {
+          const uint32_t fa =
+              (Ring<0>::read(L.h[h].ra, Hh.e.base + lane - 1) & 3u) * 0x55555555u;
+          if (h) fb2 = fa; else fa2 = fa;
+        }
+      }
+      make_uniform(Hh.e);
+      Hh.off = uni(Hh.off);
+      Hh.bd = uni(Hh.bd);
+      Hh.bln = uni(Hh.bln);
+      Hh.bxa = uni(Hh.bxa);
+    }
+  }
+}
+
+template <int ALPHA>
+__global__ __launch_bounds__(WAVE * WPB) void xd_dual_kernel(Params P) {
+  __shared__ DualLds<ALPHA> lds[WPB];
+  __shared__ int16_t tab16[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
+  if constexpr (ALPHA == 1) {
+    for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
+      tab16[i] = P.table[i];
+    __syncthreads();
+  }
+  const int wid = threadIdx.x >> 6;
+  const Src S = make_src(P);
+  run_dual<ALPHA>(P, S, lds[wid], tab16);
 }
 
 // ------------------------------------------------------------------ block
@@ -2085,6 +2573,7 @@ __device__ __forceinline__ void run_bitem(const Params& P, const Src& S,
   ItemSetup s = setup_item(P, item);
   ItemResult res;
   res.best = 0; res.x = 0; res.y = 0; res.status = s.status; res.cells = 0;
+  res.tier = -1; res.pad = 0;
   bool handed_on = false;
   if (s.status == S_OK) {
     Ext& e = s.e;
@@ -2107,7 +2596,7 @@ __device__ __forceinline__ void run_bitem(const Params& P, const Src& S,
       res.status = S_BAND;
     } else {
       res.best = e.T; res.x = e.bx; res.y = e.by; res.cells = e.W;
-      if (threadIdx.x == 0) atomicAdd(P.counters + C_TIER0 + 5, 1);
+      res.tier = 5;
     }
   }
   if (!handed_on && threadIdx.x == 0) P.items[item] = res;
@@ -2178,6 +2667,7 @@ __global__ __launch_bounds__(GEN_THREADS) void xd_general_kernel(Params P) {
     Ext& e = st.e;
     ItemResult res;
     res.best = 0; res.x = 0; res.y = 0; res.cells = 1; res.status = st.status;
+    res.tier = -1; res.pad = 0;
     // antidiagonal ranges: computed span [lo, hi] and finite range [L, U]
     int lo1 = 0, hi1 = 0, lo2 = 1, hi2 = 0;  // d-1 = 0 holds x = 0 only
     if (tid == 0) ring[0][0] = 0;
@@ -2252,7 +2742,7 @@ __global__ __launch_bounds__(GEN_THREADS) void xd_general_kernel(Params P) {
     }
     if (res.status == S_OK) {
       res.best = T; res.x = bx; res.y = by; res.cells = W;
-      if (tid == 0) atomicAdd(P.counters + C_TIER0 + 6, 1);
+      res.tier = 6;
     } else if (res.status == S_BAND) {
       res.best = 0; res.x = 0; res.y = 0; res.cells = 0;
     }
@@ -2419,19 +2909,18 @@ __global__ __launch_bounds__(1024) void xd_scatter_kernel(const int32_t* seeds, 
 }
 
 // Seed level: score = left + seed score + right and positions (Sec. 4.1.1).
-// It is the last kernel of every batch: block 0 also moves the tier counts to
-// the report slots and zeroes the other counters for the next batch (no
-// kernel of this batch uses them any more), which saves a reset launch.
-__global__ void xd_combine_kernel(Params P, void* out_v) {
-  if (blockIdx.x == 0) {
-    for (int i = threadIdx.x; i < C_REPORT; i += blockDim.x) {
-      if (i >= C_TIER0 && i < C_TIER0 + N_TIERS)
-        P.counters[C_REPORT + (i - C_TIER0)] = P.counters[i];
-      P.counters[i] = 0;
-    }
-  }
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= P.n_seeds) return;
+// It is the last kernel of every batch, so it also finishes the batch's
+// bookkeeping: block 0 zeroes the queue and ordering counters for the next
+// batch (no kernel of this batch uses them any more), which saves a reset
+// launch, and every block stores the tier counts of its seeds' extensions
+// (read from their results: ballots per wave, LDS per block) in its own
+// slots, with no atomic on device memory.
+__global__ __launch_bounds__(256) void xd_combine_kernel(Params P, void* out_v) {
+  __shared__ int hist[N_TIERS];
+  if (threadIdx.x < N_TIERS) hist[threadIdx.x] = 0;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < C_PART; i += blockDim.x) P.counters[i] = 0;
+  __syncthreads();
   struct Out {
     int32_t score, left, right, seed_score;
     int32_t q_begin, q_end, t_begin, t_end;
@@ -2439,32 +2928,55 @@ __global__ void xd_combine_kernel(Params P, void* out_v) {
     int32_t status, reserved;
   };
   Out* out = (Out*)out_v;
-  const ItemResult L = P.items[2 * (int64_t)s];
-  const ItemResult R = P.items[2 * (int64_t)s + 1];
-  Out o = {};
-  int st = L.status != S_OK ? L.status : R.status;
-  if (st == S_OK) {
-    const int* sd = P.seeds + 5 * (int64_t)s;
-    const int q = sd[0], t = sd[1], qp = sd[2], tp = sd[3], k = sd[4];
-    const int64_t oq = P.offsets[q], ot = P.offsets[t];
-    const Src S = make_src(P);
-    int seed = 0;
-    // (independent loads: unrolled so that a seed's symbols are in flight
-    // together)
+  int cnt[N_TIERS] = {};  // this wave's counts (wave-uniform)
+  // (the loop bound is uniform over the block, so every lane meets the
+  // ballots)
+  for (int s0 = blockIdx.x * blockDim.x; s0 < P.n_seeds;
+       s0 += gridDim.x * blockDim.x) {
+    const int s = s0 + (int)threadIdx.x;
+    int tl = -1, tr = -1;
+    if (s < P.n_seeds) {
+      const ItemResult L = P.items[2 * (int64_t)s];
+      const ItemResult R = P.items[2 * (int64_t)s + 1];
+      tl = L.tier;
+      tr = R.tier;
+      Out o = {};
+      int st = L.status != S_OK ? L.status : R.status;
+      if (st == S_OK) {
+        const int* sd = P.seeds + 5 * (int64_t)s;
+        const int q = sd[0], t = sd[1], qp = sd[2], tp = sd[3], k = sd[4];
+        const int64_t oq = P.offsets[q], ot = P.offsets[t];
+        const Src S = make_src(P);
+        int seed = 0;
+        // (independent loads: unrolled so that a seed's symbols are in
+        // flight together)
 #pragma unroll 16
-    for (int u = 0; u < k; ++u) {
-      const int ca = sym_at(P, S, oq + qp + u), cb = sym_at(P, S, ot + tp + u);
-      if (P.alphabet == 0) seed += (ca == cb ? P.mat_s : P.mis_s) + 2 * P.gap;
-      else seed += P.table[ca * TABLE_DIM + cb] + 2 * P.gap;
+        for (int u = 0; u < k; ++u) {
+          const int ca = sym_at(P, S, oq + qp + u), cb = sym_at(P, S, ot + tp + u);
+          if (P.alphabet == 0) seed += (ca == cb ? P.mat_s : P.mis_s) + 2 * P.gap;
+          else seed += P.table[ca * TABLE_DIM + cb] + 2 * P.gap;
+        }
+        o.left = L.best; o.right = R.best; o.seed_score = seed;
+        o.score = L.best + seed + R.best;
+        o.q_begin = qp - L.x; o.t_begin = tp - L.y;
+        o.q_end = qp + k + R.x; o.t_end = tp + k + R.y;
+        o.cells = L.cells + R.cells;
+      }
+      o.status = st;
+      out[s] = o;
     }
-    o.left = L.best; o.right = R.best; o.seed_score = seed;
-    o.score = L.best + seed + R.best;
-    o.q_begin = qp - L.x; o.t_begin = tp - L.y;
-    o.q_end = qp + k + R.x; o.t_end = tp + k + R.y;
-    o.cells = L.cells + R.cells;
+#pragma unroll
+    for (int t = 0; t < N_TIERS; ++t)
+      cnt[t] += __builtin_popcountll(ballot(tl == t)) +
+                __builtin_popcountll(ballot(tr == t));
   }
-  o.status = st;
-  out[s] = o;
+  if (lane_id() == 0)
+#pragma unroll
+    for (int t = 0; t < N_TIERS; ++t)
+      if (cnt[t]) atomicAdd(&hist[t], cnt[t]);
+  __syncthreads();
+  if (threadIdx.x < N_TIERS)
+    P.counters[C_PART + N_TIERS * blockIdx.x + threadIdx.x] = hist[threadIdx.x];
 }
 
 template __global__ void xd_wave_kernel<0, 8>(Params);
@@ -2473,6 +2985,8 @@ template __global__ void xd_pair_kernel<0>(Params);
 template __global__ void xd_pair_kernel<1>(Params);
 template __global__ void xd_block_kernel<0>(Params);
 template __global__ void xd_block_kernel<1>(Params);
+template __global__ void xd_dual_kernel<0>(Params);
+template __global__ void xd_dual_kernel<1>(Params);
 
 }  // namespace xd
 
@@ -2587,6 +3101,33 @@ int pair_blocks_per_cu(int alphabet) {
   return nb;
 }
 
+hipError_t launch_dual(const Params& P, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (P.alphabet == 0)
+    hipLaunchKernelGGL((xd_dual_kernel<0>), dim3(grid), dim3(WAVE * WPB), 0,
+                       s, P);
+  else
+    hipLaunchKernelGGL((xd_dual_kernel<1>), dim3(grid), dim3(WAVE * WPB), 0,
+                       s, P);
+  return hipGetLastError();
+}
+
+int dual_blocks_per_cu(int alphabet) {
+  int nb = 0;
+  hipError_t e =
+      alphabet == 0
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_dual_kernel<0>, WAVE * WPB, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, xd_dual_kernel<1>, WAVE * WPB, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+bool dual_exact(const Params& P) {
+  return (int64_t)P.X + (int64_t)DUAL_SPAN * P.max_abs <= 30000;
+}
+
 hipError_t launch_block(const Params& P, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (P.alphabet == 0)
@@ -2615,8 +3156,7 @@ hipError_t launch_general(const Params& P, int grid, hipStream_t s) {
 }
 
 hipError_t launch_combine(const Params& P, void* out, hipStream_t s) {
-  if (P.n_seeds <= 0) return hipSuccess;
-  hipLaunchKernelGGL(xd_combine_kernel, dim3((P.n_seeds + 255) / 256),
+  hipLaunchKernelGGL(xd_combine_kernel, dim3(combine_blocks(P.n_seeds)),
                      dim3(256), 0, s, P, out);
   return hipGetLastError();
 }

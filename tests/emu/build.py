@@ -4,10 +4,13 @@ The library's kernel and host sources are compiled with the host compiler
 against hip/hip_runtime.h of this folder (each GPU thread a fiber, the lanes
 of a wave meeting at every cross-lane operation; see emu_runtime.cpp) into
 ``_build/libxdrop_emu.so``, which exports the same C ABI as libxdrop.so.
-Two textual changes make the kernel source host C++: the GPU intrinsic name
-bound to the write-lane declaration is dropped (the runtime defines the
-function), and the register-class letters of the empty optimisation-barrier
-asm statements become the host's general class.  Nothing else differs.
+Three textual changes make the kernel source host C++: the GPU intrinsic
+name bound to the write-lane declaration is dropped (the runtime defines the
+function), the register-class letters of the empty optimisation-barrier asm
+statements become the host's general class, and the occupancy hint on kernel
+definitions (a register budget for the GPU compiler) is dropped; a trace
+hook after the wave kernel's tier loop reports the tier each extension ends
+on to the runtime.  Nothing else differs.
 The product never loads this library; only tests do.
 """
 from __future__ import annotations
@@ -28,6 +31,7 @@ CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 def host_source(text: str) -> str:
     text = re.sub(r'__asm\(\s*"llvm\.amdgcn\.writelane\.i32"\s*\)', "", text)
     text = re.sub(r'"\+[sv]"', '"+r"', text)
+    text = re.sub(r'__attribute__\(\(amdgpu_waves_per_eu\(\d+\)\)\)', "", text)
     # trace hook: the tier each extension of the wave kernel ends on
     text = re.sub(r'(r = start_tier<ALPHA, CMIN, CMAX>\(e, w, tab, P, S, start, tier\);)',
                   r'\1 emu_item_done(item, r, tier);', text)
@@ -44,7 +48,8 @@ def build(csrc: str | None = None, out: str = LIB, extra=(),
     ksrc = os.path.join(csrc, "xdrop_kernels.hip")
     with open(ksrc, encoding="utf-8") as f:
         k = host_source(f.read())
-    kout = out + ".kernels.cpp"
+    # (per-process names: test workers may build at the same time)
+    kout = f"{out}.{os.getpid()}.kernels.cpp"
     with open(kout, "w", encoding="utf-8") as f:
         f.write(k)
     srcs = [kout, os.path.join(csrc, "xdrop_host.cpp"),
@@ -53,9 +58,10 @@ def build(csrc: str | None = None, out: str = LIB, extra=(),
         srcs.append(os.path.join(csrc, "xdrop_server.cpp"))
     cmd = [CXX, "-O2", "-g", "-std=c++17", "-fPIC", "-shared",
            "-Wno-unused-command-line-argument", "-I", HERE, "-I",
-           include or os.path.join(ROOT, "include"), "-I", csrc, *extra, *srcs, "-o", out + ".tmp", "-lpthread"]
+           include or os.path.join(ROOT, "include"), "-I", csrc, *extra, *srcs, "-o", f"{out}.{os.getpid()}.tmp", "-lpthread"]
     subprocess.check_call(cmd)
-    os.replace(out + ".tmp", out)
+    os.replace(f"{out}.{os.getpid()}.tmp", out)
+    os.remove(kout)
     return out
 
 

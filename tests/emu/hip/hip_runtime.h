@@ -107,7 +107,25 @@ inline int emu_sbfe(int v, uint32_t off, uint32_t w) {
   if (off + w < 32) return (int)((uint32_t)v << (32 - off - w)) >> (32 - w);
   return v >> off;
 }
+// v_perm_b32: byte i of the result chosen by byte i of sel from the eight
+// bytes of {s0, s1} (s1 the low four); 12 gives 0x00, 13 and above 0xff,
+// 8..11 the sign of a 16-bit half (not used by the library)
+inline uint32_t emu_perm(uint32_t s0, uint32_t s1, uint32_t sel) {
+  const uint64_t v = ((uint64_t)s0 << 32) | s1;
+  uint32_t r = 0;
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t b = (sel >> (8 * i)) & 0xFF;
+    uint32_t o;
+    if (b < 8) o = (uint32_t)(v >> (8 * b)) & 0xFF;
+    else if (b == 12) o = 0;
+    else if (b >= 13) o = 0xFF;
+    else std::abort();
+    r |= o << (8 * i);
+  }
+  return r;
+}
 #define __builtin_amdgcn_alignbit(hi, lo, sh) emu_alignbit((hi), (lo), (sh))
+#define __builtin_amdgcn_perm(s0, s1, sel) emu_perm((s0), (s1), (sel))
 #define __builtin_amdgcn_ubfe(v, o, w) emu_ubfe((v), (o), (w))
 #define __builtin_amdgcn_sbfe(v, o, w) emu_sbfe((v), (o), (w))
 
@@ -124,6 +142,8 @@ inline std::common_type_t<A, B> max(A a, B b) {
 
 template <class T>
 inline T atomicAdd(T* p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+template <class T>
+inline T atomicExch(T* p, T v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
 template <class T>
 inline T atomicMax(T* p, T v) {
   T o = __atomic_load_n(p, __ATOMIC_SEQ_CST);

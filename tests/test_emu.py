@@ -205,3 +205,26 @@ def test_seeds_share_sequences(emu):
     g = emu.run(shared, sc)
     assert not compare(g, emu.run(unique, sc))
     assert not compare(g, oracle_run(shared, scheme))
+
+
+@pytest.mark.parametrize("alphabet,X", [(20, 49), (4, 15), (4, 0)])
+def test_dual16_kernel(emu, alphabet, X):
+    """The two-extension 16-bit kernel on the CPU build: fuzz batches, a
+    long-extension sample (ring wrap), hand-on of wide bands."""
+    rng = np.random.default_rng([93, alphabet, X])
+    b = make_batch(_fuzz(rng, 60, alphabet, 700), alphabet)
+    s = (inputs.Scheme(4, 2, -3, -2, X) if alphabet == 4 else
+         inputs.Scheme(20, gap=-2, X=X,
+                       matrix=inputs.stand_in_substitution_matrix()))
+    g = emu.run(b, product_scoring(s), xdrop.options(variant=5))
+    assert not compare(g, oracle_run(b, s))
+    assert emu.last_stats()[7] > 0
+
+
+def test_dual16_long_extensions(emu):
+    b, s = inputs.workload("dna-tail", 1.0)
+    n = len(b.seeds)
+    b = b.subset([n - 1, n - 2, 0, 1])
+    g = emu.run(b, product_scoring(s), xdrop.options(variant=5))
+    assert not compare(g, oracle_run(b, s))
+    assert emu.last_stats()[7] == 8

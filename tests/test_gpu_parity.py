@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 from paper_2304_08662_amd import inputs
-from tests.xdrop_testutil import (Runner, compare, make_batch, oracle_run)
+from tests.xdrop_testutil import (Runner, compare, make_batch, oracle_run,
+                                  product_scoring)
 
 pytestmark = pytest.mark.gpu
 
@@ -170,7 +171,7 @@ def test_variants_identical(runner):
     for v, tile, chunk, order in [(1, 1, 1, 0), (1, 2, 3, 0), (1, 4, 8, 1),
                                   (1, 8, 64, 0), (3, 1, 1, 0), (3, 8, 1, 1),
                                   (2, 1, 1, 0), (4, 1, 1, 0), (4, 2, 4, 1),
-                                  (4, 8, 1, 0)]:
+                                  (4, 8, 1, 0), (5, 1, 1, 0), (5, 1, 1, 1)]:
         o = xdrop.options(v, tile, chunk, 0, order)
         g = runner.run(batch, scheme, o, dev=dev)
         bad = compare(g, ref)
@@ -293,6 +294,53 @@ def test_seeds_share_sequences(runner, alphabet):
     assert not compare(g_shared, oracle_run(shared, scheme))
 
 
+def _dual_cases():
+    rng = np.random.default_rng(91)
+    M = inputs.stand_in_substitution_matrix()
+    cases = []
+    for alpha, X in ((20, 49), (20, 0), (4, 15), (4, 50)):
+        b = make_batch(_fuzz_pairs(rng, 300, alpha, 700), alpha)
+        s = (inputs.Scheme(4, 2, -3, -2, X) if alpha == 4 else
+             inputs.Scheme(20, gap=-2, X=X, matrix=M))
+        cases.append((f"fuzz-{alpha}-{X}", b, s))
+    b, s = inputs.workload("dna-tail", 1.0)
+    n = len(b.seeds)
+    cases.append(("dna-tail-long", b.subset(list(range(n - 10, n))), s))
+    b, s = inputs.workload("protein-500k", 0.002)
+    cases.append(("protein-500k-0.002", b, s))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_dual16_kernel(runner, case):
+    """The two-extension 16-bit kernel (XDROP_VARIANT_DUAL16) against the
+    oracle: fuzz batches of both alphabets, 50-100 kb extensions whose
+    sequences wrap the LDS rings many times, a protein-500k sample; most
+    extensions finish on it, wide bands are handed on to the wave kernel."""
+    from paper_2304_08662_amd import xdrop
+    name, b, s = _dual_cases()[case]
+    ref = oracle_run(b, s)
+    g = runner.run(b, s, xdrop.options(variant=5))
+    bad = compare(g, ref)
+    assert not bad, (name, bad[:5])
+    stats = runner.ctx.last_stats()
+    assert stats[7] > 0 and sum(stats) == 2 * len(b.seeds), (name, stats)
+
+
+def test_dual16_falls_back_to_int32(runner):
+    """Where relative 16-bit scores could overflow (large X), the batch runs
+    on the int32 kernels, with the same results."""
+    from paper_2304_08662_amd import xdrop
+    rng = np.random.default_rng(92)
+    b = make_batch(_fuzz_pairs(rng, 100, 4, 500), 4)
+    s = inputs.Scheme(4, 1, -1, -1, 31000)
+    g = runner.run(b, s, xdrop.options(variant=5))
+    assert not compare(g, oracle_run(b, s))
+    assert runner.ctx.last_stats()[7] == 0
+    assert runner.ctx.resolve_options(product_scoring(s), len(b.seeds),
+                                      xdrop.options(variant=5)).variant == 1
+
+
 def test_statuses(runner):
     from paper_2304_08662_amd import xdrop
     rng = np.random.default_rng(25)
@@ -336,7 +384,7 @@ def test_invalid_arguments(runner):
     with pytest.raises(xdrop.XdropError):
         runner.run(batch, inputs.Scheme(4, 1, -1, -1, -1))
     with pytest.raises(xdrop.XdropError):
-        runner.run(batch, inputs.Scheme(4, 1, -1, -1, 5), xdrop.options(variant=5))
+        runner.run(batch, inputs.Scheme(4, 1, -1, -1, 5), xdrop.options(variant=6))
 
 
 def test_graph_replay(runner):
