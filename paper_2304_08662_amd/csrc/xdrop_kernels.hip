@@ -42,6 +42,9 @@
 
 #include "xdrop_internal.h"
 
+#ifndef XD_KB1
+#define XD_KB1 48  // antidiagonals per block of the one-cell loop
+#endif
 namespace xd {
 
 // ------------------------------------------------------------------ helpers
@@ -216,7 +219,9 @@ template <int RS_, int NT>
 struct RingT<1, RS_, NT> {  // one byte per code
   static constexpr int RS = RS_;
   static constexpr int RW = RS / 4;
-  static constexpr int MIRROR = 9;         // reads of up to 8 words
+  // reads of up to 8 words, and the one-cell loop's per-lane code reads up
+  // to XD_KB1 + 2 bytes past a position
+  static constexpr int MIRROR = (XD_KB1 + 6) / 4 > 9 ? (XD_KB1 + 6) / 4 : 9;
   static constexpr int WORDS = RW + MIRROR;
   static constexpr int CH = 8 * NT;        // elements per fill (8 per thread)
 
@@ -608,7 +613,7 @@ __device__ __forceinline__ int in_vgpr(int v) {
 // scalar ranges (positions relative to the window base):
 //   lo_d = max(ctz(M1 | M2 << 1), d - n - base),
 //   hi_d = min(64 - clz(M1 | M2), m - base),
-// where the clamps matter only near the matrix edges; blocks of 32
+// where the clamps matter only near the matrix edges; blocks of XD_KB1
 // antidiagonals that stay clear of both edges skip them and the per-lane
 // edge masks.  The live-span count
 // sum(hi_d - lo_d + 1) is formed once per block on the vector unit from the
@@ -681,13 +686,16 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   int pm = 0, mrel = 0;     // d - n - base, m - base (edge clamps and masks)
   uint64_t in_m = 0;        // edge blocks: the lanes with x <= m
   int rem = 0;              // edge blocks: d_end - d
-  // antidiagonals per block (the block's fixed work spreads over 32
-  // steps): DNA reads two match words, bytes 32 target codes into qw
-  constexpr int KB = 32;
+  // antidiagonals per block (the block's fixed work, some 60 vector
+  // instructions, spreads over its steps; 48 measured 3-5% faster than 32):
+  // DNA reads KB / 16 match words, bytes take their codes from the ring
+  constexpr int KB = XD_KB1;
+  static_assert(KB % 16 == 0 && KB + 2 <= 64,
+                "whole DNA match words; the masks of a block fit in 64 lanes");
   // top lanes kept -infinity between the tests against the top, which run
   // with the dead test, every fourth antidiagonal
   constexpr int G = 4;
-  uint32_t mw[2] = {0, 0};  // DNA: match words of the block (k < 16, >= 16)
+  uint32_t mw[KB / 16] = {};  // DNA: match words of the block (16 steps each)
   // finite-lane masks of the block's antidiagonals for the live-span count,
   // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
   // the two antidiagonals before the block, lane k + 2 the block's k-th
@@ -812,15 +820,15 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + KB - 1);
     if constexpr (ALPHA == 0) {
-      // codes of b[e0 - lane - 1 + k], k < 32, against the lane's query code
+      // codes of b[e0 - lane - 1 + k], k < KB, against the lane's query code
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < KB / 16; ++h) {
         const uint32_t xw = Ring<0>::read(w.rb, e0 - lane - 1 + 16 * h) ^ fa;
         mw[h] = ~(xw | (xw >> 1)) & 0x55555555u;
       }
     } else {
-      // (reads up to 34 bytes past a position of the ring, which its mirror
-      // words cover; codes past those covered belong to no block step)
+      // (reads up to KB + 2 bytes past a position of the ring, which its
+      // mirror words cover; codes past those covered belong to no block step)
       cp = reinterpret_cast<const uint8_t*>(w.rb) +
            ((e0 - lane - 1) & (Ring<1>::RS - 1));
       sc_next = score(cp[0]);
