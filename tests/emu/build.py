@@ -10,7 +10,9 @@ function), the register-class letters of the empty optimisation-barrier asm
 statements become the host's general class, and the occupancy hint on kernel
 definitions (a register budget for the GPU compiler) is dropped; a trace
 hook after the wave kernel's tier loop reports the tier each extension ends
-on to the runtime.  Nothing else differs.
+on to the runtime, and every shared-memory declaration registers its
+variable, which the runtime fills with garbage once per block (no code may
+read LDS it has not written).  Nothing else differs.
 The product never loads this library; only tests do.
 """
 from __future__ import annotations
@@ -32,6 +34,13 @@ def host_source(text: str) -> str:
     text = re.sub(r'__asm\(\s*"llvm\.amdgcn\.writelane\.i32"\s*\)', "", text)
     text = re.sub(r'"\+[sv]"', '"+r"', text)
     text = re.sub(r'__attribute__\(\(amdgpu_waves_per_eu\(\d+\)\)\)', "", text)
+    # shared variables start with garbage in every block
+    def _shared(m):
+        names = re.findall(r'(\w+)\s*(?:\[[^\]]*\])?\s*(?:,|$)', m.group(2))
+        return m.group(0) + "".join(
+            f" emu::shared_decl(&{n}, sizeof({n}));" for n in names)
+    text = re.sub(r'^(\s*)__shared__\s+(?:[\w:<>, ]+?\s+)?((?:\w+\s*(?:\[[^\]]*\])?\s*,?\s*)+);',
+                  _shared, text, flags=re.M)
     # trace hook: the tier each extension of the wave kernel ends on
     text = re.sub(r'(r = start_tier<ALPHA, CMIN, CMAX>\(e, w, tab, P, S, start, tier\);)',
                   r'\1 emu_item_done(item, r, tier);', text)

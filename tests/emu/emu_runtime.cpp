@@ -98,6 +98,27 @@ struct Block {
 };
 
 static thread_local Block* g_blk = nullptr;
+static std::atomic<uint64_t> g_block_gen{0};
+static thread_local uint64_t g_cur_gen = 0;  // this OS thread's block
+static thread_local std::vector<std::pair<void*, uint64_t>> g_shared;
+
+void shared_decl(void* p, size_t n) {
+  for (auto& e : g_shared)
+    if (e.first == p) {
+      if (e.second == g_cur_gen) return;
+      e.second = g_cur_gen;
+      goto fill;
+    }
+  g_shared.emplace_back(p, g_cur_gen);
+fill:
+  // a different pattern per block: nothing may depend on it
+  uint64_t x = g_cur_gen * 0x9E3779B97F4A7C15ull + 0x5A5A5A5A5A5A5A5Aull;
+  unsigned char* q = (unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+    q[i] = (unsigned char)x;
+  }
+}
 
 Fiber* cur() { return g_blk->cur; }
 const Idx& thread_idx() { return g_blk->cur->tid; }
@@ -138,6 +159,7 @@ static void init_fiber(Fiber& f) {
 
 static void run_block(Block& b) {
   g_blk = &b;
+  g_cur_gen = ++g_block_gen;
   for (int i = 0; i < b.n; ++i) {
     Fiber& f = b.fibers[i];
     f.tid = Idx{(unsigned)(i % b.bdim.x), (unsigned)(i / b.bdim.x % b.bdim.y),

@@ -65,6 +65,10 @@ void wave_sync();
 void syncthreads();
 using KernelThunk = void (*)(void*);
 void launch(KernelThunk fn, void* args, dim3 grid, dim3 block);
+// a block's shared variable, filled with garbage when the block's first
+// thread reaches its declaration (as on the GPU, where LDS starts with
+// whatever the previous workgroup left)
+void shared_decl(void* p, size_t n);
 }  // namespace emu
 
 // trace hook (tests/emu/build.py inserts the calls)
