@@ -1393,11 +1393,13 @@ __device__ __forceinline__ void run_item(const Params& P, const Src& S, int item
 
 // Persistent wave kernel: extensions of the batch pulled from the queue in
 // chunks of P.chunk (or, in the plain form, one per launched wave), tiles of
-// 1..CMAX cells per lane.  Occupancy target six waves per SIMD: the compiler
-// then keeps the kernel within 80 registers per lane, and the one-cell loop,
-// bound by vector issue with dependent steps, gains from the sixth wave.
+// 1..CMAX cells per lane.  Occupancy targets, measured: six waves per SIMD
+// for DNA (the compiler then keeps the kernel within 80 registers per lane;
+// the one-cell loop, bound by issue with dependent steps, gains from the
+// sixth wave) and seven for byte codes (72 registers, a few spills outside
+// the sweep; 2.5% faster on protein-500k, while seven cost DNA 2%).
 template <int ALPHA, int CMAX>
-__global__ __launch_bounds__(WAVE * WPB) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(WAVE * WPB) __attribute__((amdgpu_waves_per_eu(ALPHA == 1 ? 7 : 6)))
 void xd_wave_kernel(Params P) {
   constexpr int CMIN = 1;
   __shared__ WaveLds<ALPHA> lds[WPB];
@@ -1448,38 +1450,66 @@ void xd_wave_kernel(Params P) {
 }
 
 // ------------------------------------------------------------------ pairs
-// Two extensions per wavefront for narrow bands.  Lanes 0-31 run extension
-// A and lanes 32-63 extension B with one cell per lane, a 32-cell window
-// each (lane 32*h + p holds window position p of half h).  Both advance
-// antidiagonal by antidiagonal in lockstep, so every vector instruction of
-// the sweep serves two extensions; the scalar bookkeeping runs on the two
-// 32-bit halves of each ballot.  As in the one-cell loop of the wave kernel:
-//  * the band bookkeeping uses the finite-lane ballots M1, M2 of the last two
-//    antidiagonals: per half lo = ctz(M1 | M2 << 1), hi = 32 - clz(M1 | M2),
-//    live-span cells 33 - (ctz + clz).  Adding min(ctz + clz, 33) keeps the
-//    sum exact after a half has died (both searches then return -1);
-//  * the top lane of each half stays -infinity (the window slides up in
-//    place when the band reaches it), so a wave rotation feeds lanes 0 and
-//    32 the -infinity of the other half's top lane;
-//  * blocks of 16 antidiagonals clear of the matrix edges skip the edge
-//    masks and clamps.
+// Two extensions per wavefront for narrow bands.  Lanes 0-31 run one
+// extension and lanes 32-63 another, one cell per lane, a 32-cell window
+// each (lane 32h + p holds window position p of half h), so every vector
+// instruction of the sweep serves both.  Each half keeps its own
+// antidiagonal, window and scalar state, and takes the next extension from
+// the queue when its own ends.  The sweep is the one-cell loop of the wave
+// kernel on two windows:
+//  * blocks of PKB antidiagonals on finite-lane ballots, whose two 32-bit
+//    halves are the two windows' masks; blocks clear of the matrix edges of
+//    both windows skip the edge masks;
+//  * the top G lanes of each window are -infinity at the start of every
+//    group of G antidiagonals, so the wave rotation brings -infinity to
+//    lanes 0 and 32, and the band is tested against the top every G-th
+//    step; a band that reaches the top slides its window up in place
+//    (`ds_bpermute` within the half);
+//  * thresholds are per lane: a lane compares v - T0 of its window (T in the
+//    frame of the block's first antidiagonal) with constants that move by
+//    -gap per antidiagonal;
+//  * live-span cells are counted per block and window from the masks kept
+//    in lanes of two registers (one per window);
+//  * byte scores come from per-lane ring reads at immediate offsets, DNA
+//    scores from per-block match words.
 // An extension whose band fills its 32-cell window is handed on to the wave
-// kernel, which restarts it.  The two extensions come from consecutive slots
-// of the longest-first order, so their lengths are close; the wave takes the
-// next pair once both are done.
+// kernel, which restarts it.
+// State of a window's extension that the sweep does not touch between
+// block boundaries; it stays in LDS, so that the block keeps its scalar
+// registers for the sweep.
+struct PairCold {
+  int64_t a_start, b_start, W;  // sources, live-span cells so far
+  int a_dir, b_dir, loaded_a, loaded_b;  // ring levels
+  int bxa, tbest;               // last new best: x and V value
+};
+
 template <int ALPHA>
 struct PairLds {
   WaveLds<ALPHA> h[2];
+  PairCold c[2];
 };
 
+// Uniform state of one window's extension kept in scalar registers.
 struct PairHalf {
-  Ext e;
-  int item;
-  int own;       // this kernel writes the result
-  int alive;     // a finite cell on one of the last two antidiagonals
-  uint32_t acc;  // this block: sum of (33 - live-span cells) per antidiagonal
-  int tbest, bd, bxa;  // last new best: V value, antidiagonal, x
+  int item;         // -1: none
+  int m, n;         // lengths
+  int d, base;      // next antidiagonal, window position 0 = x of base
+  int tv0;          // T in the V frame of antidiagonal d
+  int bd, bln;      // last new best: antidiagonal and lane (bd < 0: none)
+  uint32_t m1, m2;  // finite lanes of d - 1 and d - 2
 };
+
+// Fills a window's ring up to element need_hi (see cover_a / cover_b).
+template <int ALPHA>
+__device__ __forceinline__ void pair_cover(uint32_t* ring, const Src& S,
+                                           int64_t start, int dir,
+                                           int& loaded, int need_hi) {
+  while (loaded <= need_hi) {
+    Ring<ALPHA>::fill(ring, S, start, dir, loaded, lane_id());
+    loaded += Ring<ALPHA>::CH;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
 
 // Maxima of v over the lanes of each half.
 __device__ __forceinline__ void half_max(int v, int& h0, int& h1) {
@@ -1491,283 +1521,355 @@ __device__ __forceinline__ void half_max(int v, int& h0, int& h1) {
   h1 = smax(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
 }
 
-// Each 32-bit half of m shifted right by its own amount.
-__device__ __forceinline__ uint64_t shift_halves(uint64_t m, int s0, int s1) {
-  return (uint64_t)((uint32_t)m >> s0) |
-         ((uint64_t)((uint32_t)(m >> 32) >> s1) << 32);
+constexpr int PKB = 48;  // antidiagonals per block of the pair sweep
+
+// Result of a finished window's extension.
+__device__ __forceinline__ void pair_finish(const Params& P, const PairHalf& H,
+                                            const PairCold& c, int gap) {
+  ItemResult r;
+  r.status = S_OK;
+  r.cells = uni64(c.W);
+  r.tier = 4; r.pad = 0;
+  if (H.bd >= 0) {
+    const int bxa = uni(c.bxa);
+    r.best = uni(c.tbest) + gap * H.bd;
+    r.x = bxa;
+    r.y = H.bd - bxa;
+  } else {
+    r.best = 0; r.x = 0; r.y = 0;
+  }
+  if (lane_id() == 0) P.items[H.item] = r;
 }
 
 template <int ALPHA>
-__device__ __forceinline__ void run_pair(const Params& P, const Src& S,
-                                         int item0, int item1,
-                                         PairLds<ALPHA>& L, const int* tab) {
-  constexpr uint64_t TOPS = (1ull << 31) | (1ull << 63);
+__device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
+                                          PairLds<ALPHA>& L, const int* tab) {
+  constexpr int KB = PKB;
+  static_assert(KB % 16 == 0 && KB + 2 <= 64, "match words; mask lanes");
+  constexpr int G = 4;
+  constexpr int BIG = 1 << 29;  // T of an idle window: no cell passes
   const int lane = lane_id();
   const int hf = lane >> 5, p = lane & 31;
-  PairHalf H[2];
-  const int items[2] = {item0, item1};
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    H[h].item = items[h];
-    H[h].own = 0;
-    H[h].alive = 0;
-    H[h].acc = 0;
-    H[h].tbest = 0;
-    H[h].bd = -1;
-    H[h].bxa = 0;
-    H[h].e.base = 0;
-    H[h].e.m = H[h].e.n = 0;
-    if (items[h] < 0) continue;
-    ItemSetup st = setup_item(P, items[h]);
-    H[h].e = st.e;
-    if (st.status != S_OK || st.e.m + st.e.n == 0) {
-      ItemResult r;
-      r.best = 0; r.x = 0; r.y = 0; r.status = st.status;
-      r.cells = st.status == S_OK ? 1 : 0;
-      r.tier = st.status == S_OK ? 4 : -1; r.pad = 0;
-      if (lane == 0) P.items[items[h]] = r;
-      continue;
-    }
-    H[h].own = 1;
-    H[h].alive = 1;
-    cover_a<ALPHA>(H[h].e, L.h[h], S, 30);
-    cover_b<ALPHA>(H[h].e, L.h[h], S, 0);
-  }
-  if (!H[0].alive && !H[1].alive) return;
-
-  const uint32_t* ra_l = hf ? L.h[1].ra : L.h[0].ra;
-  const uint32_t* rb_l = hf ? L.h[1].rb : L.h[0].rb;
+  const bool in1 = hf != 0;
   const int gap = P.gap, X = smin(P.X, 1 << 29);  // see fast_interior
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
-  auto code_a = [&](int idx) -> int {
+  PairHalf H[2];
+  H[0].item = H[1].item = -1;
+  H[0].m1 = H[0].m2 = H[1].m1 = H[1].m2 = 0;  // (idle windows: no lanes)
+  H[0].d = H[1].d = H[0].base = H[1].base = 0;
+  H[0].m = H[1].m = H[0].n = H[1].n = 0;
+  int x = NEG, y = NEG;  // antidiagonals d-1 and d-2 of the lane's window
+  // DNA: the lane's query code in all 16 code slots of a word; bytes: the
+  // byte offset of its score-table row
+  uint32_t fa = 0;
+  auto load_fa = [&](int h) {
+    const uint32_t* ra = L.h[h].ra;
+    uint32_t f;
     if constexpr (ALPHA == 0) {
-      return (int)(Ring<0>::read(ra_l, idx) & 3u);
+      f = (Ring<0>::read(ra, H[h].base + p - 1) & 3u) * 0x55555555u;
     } else {
       uint32_t t[1];
-      Ring<1>::read<1>(ra_l, idx, t);
-      return (int)(t[0] & 31u) << 5;
+      Ring<1>::read<1>(ra, H[h].base + p - 1, t);
+      f = (t[0] & 31u) << 7;
     }
+    fa = hf == h ? f : fa;
   };
-  auto code_b = [&](int idx) -> int {
-    if constexpr (ALPHA == 0) {
-      return (int)(Ring<0>::read(rb_l, idx) & 3u);
-    } else {
-      uint32_t t[1];
-      Ring<1>::read<1>(rb_l, idx, t);
-      return (int)(t[0] & 31u);
-    }
+  auto score = [&](uint32_t c) {
+    return *reinterpret_cast<const int*>(
+        reinterpret_cast<const char*>(tab) + fa + (c << 2));
   };
-  int d = 1;
-  int base_l = 0;
-  int fa = code_a(p - 1);
-  int fb = code_b(d - p - 1);
-  const bool run_l = hf ? H[1].alive : H[0].alive;
-  int x = (p == 0 && run_l) ? 0 : NEG;  // antidiagonal 0: S(0,0) = 0
-  int y = NEG;
-  uint64_t m1 = (H[0].alive ? 1ull : 0ull) | (H[1].alive ? 1ull << 32 : 0ull);
-  uint64_t m2 = 0;
-  int tv_v = -gap;  // best score in the frame of antidiagonal d (T = 0)
-  int thr_v = tv_v - X;
-  int pm[2] = {0, 0}, mrel[2] = {0, 0};  // edge blocks: d - n - base, m - base
-  int pm_v = 0, mrel_v = 0;
-
-  // Antidiagonal d of both extensions from prev (d-1) and pp (d-2); pp
-  // receives d, then the target codes move one cell up and lanes 0 and 32
-  // take `in` (b[d - base - 1] of their extension).  Returns 1 when a top
-  // lane turned finite.
-  auto body = [&](auto edge_tag, int& prev, int& pp, int in) -> int {
-    constexpr bool EDGE = decltype(edge_tag)::value;
-    const uint64_t clo = m1 | (m2 << 1), chi = m1 | m2;
+  bool drained = false;
+  int cur = 0, end = 0;  // queue slots claimed, P.chunk at a time
+  for (;;) {
+    // idle windows take the next extensions
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const uint32_t lo = (uint32_t)(clo >> (32 * h));
-      const uint32_t hi = (uint32_t)(chi >> (32 * h));
-      if constexpr (EDGE) {
-        const int c = (int)__builtin_ctzg(lo, 32);
-        const int z = (int)__builtin_clzg(hi, 32);
-        const int w = smax(smin(32 - z, mrel[h]) - smax(c, pm[h]) + 1, 0);
-        H[h].acc += (uint32_t)(33 - w);
-      } else {
-        const uint32_t t = (uint32_t)__builtin_ctzg(lo, -1) +
-                           (uint32_t)__builtin_clzg(hi, -1);
-        H[h].acc += t < 33u ? t : 33u;
+      while (H[h].item < 0 && !drained) {
+        if (cur >= end) {
+          int c = 0;
+          if (lane == 0) c = atomicAdd(P.counters + C_PAIR_HEAD, P.chunk);
+          cur = uni(c);
+          end = min(cur + P.chunk, P.n_items);
+          if (cur >= P.n_items) { drained = true; break; }
+        }
+        const int c = cur++;
+        const int item = (P.flags & F_ORDERED) ? uni(P.order[c]) : c;
+        ItemSetup st = setup_item(P, item);
+        if (st.status != S_OK || st.e.m + st.e.n == 0) {
+          ItemResult r;
+          r.best = 0; r.x = 0; r.y = 0; r.status = st.status;
+          r.cells = st.status == S_OK ? 1 : 0;
+          r.tier = st.status == S_OK ? 4 : -1; r.pad = 0;
+          if (lane == 0) P.items[item] = r;
+          continue;
+        }
+        PairHalf& Hh = H[h];
+        Hh.item = item;
+        Hh.m = st.e.m; Hh.n = st.e.n;
+        Hh.d = 1; Hh.base = 0;
+        Hh.tv0 = -gap;  // T = 0 in the frame of antidiagonal 1
+        Hh.bd = -1; Hh.bln = 0;
+        Hh.m1 = 1;  // antidiagonal 0: S(0,0) = 0 at window position 0
+        Hh.m2 = 0;
+        x = hf == h ? (p == 0 ? 0 : NEG) : x;
+        y = hf == h ? NEG : y;
+        int la = 0;
+        pair_cover<ALPHA>(L.h[h].ra, S, st.e.a_start, st.e.a_dir, la, 30);
+        PairCold& pc = L.c[h];
+        pc.a_start = st.e.a_start; pc.b_start = st.e.b_start; pc.W = 1;
+        pc.a_dir = st.e.a_dir; pc.b_dir = st.e.b_dir;
+        pc.loaded_a = la; pc.loaded_b = 0;
+        pc.bxa = 0; pc.tbest = 0;
+        __builtin_amdgcn_wave_barrier();
+        load_fa(h);
       }
     }
-    const int up = __builtin_amdgcn_mov_dpp(prev, 0x13C, 0xf, 0xf, false);
-    const int dg = __builtin_amdgcn_mov_dpp(pp, 0x13C, 0xf, 0xf, false);
-    int sim;
-    if constexpr (ALPHA == 0) sim = fa == fb ? vmat : vmis;
-    else sim = tab[fa + fb];
-    const int v = max(max(up, prev), dg + sim);
-    bool f = v >= thr_v;
-    // y > n below pm, x > m above mrel (past antidiagonal m + n the range
-    // is empty: pm > mrel)
-    if constexpr (EDGE) f = f && p >= pm_v && p <= mrel_v;
-    const int vn = f ? v : NEG;
-    const uint64_t fm = ballot(f);
-    const uint64_t imp = ballot(vn > tv_v);
-    pp = vn;
-    if (imp) {
+    const bool live0 = H[0].item >= 0, live1 = H[1].item >= 0;
+    if (!live0 && !live1) break;
+
+    // ---- one block of antidiagonals of both windows
+    int pm[2], mrel[2], rem[2], d0[2], e0[2];
+    bool edge = false;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t ih = (uint32_t)(imp >> (32 * h));
-        if (ih) {
-          int l = __builtin_ctz(ih);
-          int wm = __builtin_amdgcn_readlane(vn, 32 * h + l);
-          if (ih & (ih - 1)) {
-            int a0, a1;
-            half_max(vn, a0, a1);
-            wm = h ? a1 : a0;
-            l = __builtin_ctz((uint32_t)(ballot(vn == wm) >> (32 * h)));
+    for (int h = 0; h < 2; ++h) {
+      PairHalf& Hh = H[h];
+      if (Hh.item < 0) {
+        pm[h] = -KB; mrel[h] = 31; rem[h] = KB; d0[h] = 0; e0[h] = 0;
+        continue;
+      }
+      d0[h] = Hh.d;
+      pm[h] = Hh.d - Hh.n - Hh.base;
+      mrel[h] = Hh.m - Hh.base;
+      rem[h] = Hh.m + Hh.n - Hh.d;  // antidiagonals left after d
+      if (!(pm[h] + KB - 1 <= 0 && mrel[h] >= 31 && rem[h] >= KB - 1))
+        edge = true;
+      e0[h] = Hh.d - Hh.base;
+      PairCold& c = L.c[h];
+      int lb = uni(c.loaded_b);
+      if (lb <= e0[h] + KB - 1) {
+        pair_cover<ALPHA>(L.h[h].rb, S, uni64(c.b_start), uni(c.b_dir), lb,
+                          e0[h] + KB - 1);
+        c.loaded_b = lb;
+      }
+    }
+    // per lane: its window's values
+    const int pq = p - (in1 ? pm[1] : pm[0]);  // y <= n from step pq on...
+    const uint64_t in_m = ballot(p <= (in1 ? mrel[1] : mrel[0]));
+    int tv0_v = in1 ? (live1 ? H[1].tv0 : BIG) : (live0 ? H[0].tv0 : BIG);
+    const int e0_l = in1 ? e0[1] : e0[0];
+    uint32_t mw[KB / 16] = {};  // DNA: match words of the block
+    const uint8_t* cp = reinterpret_cast<const uint8_t*>(in1 ? L.h[1].rb
+                                                              : L.h[0].rb);
+    int sc_next = 0;
+    uint32_t cd1 = 0, cd2 = 0;
+    if constexpr (ALPHA == 0) {
+      const uint32_t* rb = in1 ? L.h[1].rb : L.h[0].rb;
+#pragma unroll
+      for (int i = 0; i < KB / 16; ++i) {
+        const uint32_t xw = Ring<0>::read(rb, e0_l - p - 1 + 16 * i) ^ fa;
+        mw[i] = ~(xw | (xw >> 1)) & 0x55555555u;
+      }
+    } else {
+      cp += (e0_l - p - 1) & (Ring<1>::RS - 1);
+      sc_next = score(cp[0]);
+      cd1 = cp[1];
+      cd2 = cp[2];
+    }
+    // finite-lane masks of the block's antidiagonals per window, in lanes of
+    // ml (window 0) and mh (window 1): lanes 0 and 1 the two antidiagonals
+    // before the block, lane k + 2 the k-th
+    int ml = 0, mh = 0;
+    ml = xd_writelane_i32((int)H[0].m2, 0, ml);
+    mh = xd_writelane_i32((int)H[1].m2, 0, mh);
+    ml = xd_writelane_i32((int)H[0].m1, 1, ml);
+    mh = xd_writelane_i32((int)H[1].m1, 1, mh);
+    uint64_t a1 = (uint64_t)H[0].m1 | ((uint64_t)H[1].m1 << 32);
+    uint64_t a2 = (uint64_t)H[0].m2 | ((uint64_t)H[1].m2 << 32);
+    int tv0s[2] = {H[0].tv0, H[1].tv0};
+    int bd[2] = {H[0].bd, H[1].bd}, bln[2] = {H[0].bln, H[1].bln};
+    int tb[2] = {0, 0};  // V value of a new best of this block
+    int nk = KB;
+    bool newest_in_y = false;
+    // running -k * gap and -k * gap - X of step k (set for k = -1)
+    uint32_t ck = (uint32_t)gap, thc = (uint32_t)(gap - X);
+    // antidiagonal d_h + k of both windows from prev (d-1, masks mp) and pp
+    // (d-2, masks mpp); pp and mpp receive d.  True when a live window's band
+    // reached its top lanes or had two dead antidiagonals (tested every G),
+    // or at a window's last antidiagonal (edge blocks).
+    auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
+                    uint64_t& mpp, int k) -> bool {
+      constexpr bool EDGE = decltype(edge_tag)::value;
+      int sim;
+      if constexpr (ALPHA == 0) {
+        int t = __builtin_amdgcn_sbfe((int)mw[k >> 4], 2 * (k & 15), 1);
+        opaque_v(t);  // (one v_bfi below, not compare + select)
+        sim = (t & vmat) | (~t & vmis);
+        opaque_v(sim);
+      } else {
+        sim = sc_next;
+        sc_next = score(cd1);
+        cd1 = cd2;
+        cd2 = cp[k + 3];
+      }
+      const int up = __builtin_amdgcn_update_dpp(0, prev, 0x13C, 0xf, 0xf, true);
+      const int dg = __builtin_amdgcn_update_dpp(0, pp, 0x13C, 0xf, 0xf, true);
+      int uh = max(up, prev);
+      opaque_v(uh);
+      const int v = max(uh, dg + sim);
+      // T of the lane's window at this antidiagonal is T0 + ck (ck and the
+      // threshold move by -gap per step: kept as running scalars, which the
+      // compiler would otherwise precompute for every step of the block)
+      ck -= gap;
+      thc -= gap;
+      opaque_s(ck);
+      opaque_s(thc);
+      const int t = v - tv0_v;
+      uint64_t fm = ballot(t >= (int)thc);
+      if constexpr (EDGE)  // y > n below pm + k, x > m above mrel
+        fm &= ballot(pq >= k) & in_m;
+      const int vn = __builtin_amdgcn_inverse_ballot_w64(fm) ? v : NEG;
+      uint64_t imp = ballot(t > (int)ck);
+      if constexpr (EDGE) imp &= fm;
+      int vk = vn;
+      pin_v(vk);
+      pp = vk;
+      if (__builtin_expect(imp != 0, 0)) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t ih = (uint32_t)(imp >> (32 * h));
+          if (!ih) continue;
+          int l0 = __builtin_ctz(ih);
+          int wm = __builtin_amdgcn_readlane(vn, 32 * h + l0);
+          if (__builtin_popcount(ih) > 1) {
+            int a0, b0;
+            half_max(vn, a0, b0);
+            wm = h ? b0 : a0;
+            l0 = __builtin_ctz((uint32_t)(ballot(vn == wm) >> (32 * h)));
           }
-          H[h].tbest = wm;  // T, bx, by are formed at the end
-          H[h].bd = d;
-          H[h].bxa = H[h].e.base + l;
-          const int wv = in_vgpr(wm);
-          tv_v = hf == h ? wv : tv_v;
-          thr_v = hf == h ? wv - X : thr_v;
+          tv0s[h] = wm - (int)ck;
+          tv0_v = hf == h ? wm - (int)ck : tv0_v;
+          bd[h] = d0[h] + k;
+          bln[h] = l0;
+          tb[h] = wm;
         }
       }
-    }
-    m2 = m1;
-    m1 = fm;
-    tv_v -= gap;
-    thr_v -= gap;
-    ++d;
-    if constexpr (EDGE) {
-      ++pm[0];
-      ++pm[1];
-      ++pm_v;
-    }
-    fb = __builtin_amdgcn_update_dpp(in, fb, 0x138, 0xf, 0xf, false);
-    fb = lane == 32 ? in : fb;
-    return (fm & TOPS) ? 1 : 0;
-  };
-
-  bool newest_in_y = false;
-  for (;;) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-      H[h].alive = (uint32_t)((m1 | m2) >> (32 * h)) != 0;
-    if (!H[0].alive && !H[1].alive) break;
-    bool interior = true;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      pm[h] = d - H[h].e.n - H[h].e.base;
-      mrel[h] = H[h].e.m - H[h].e.base;
-      if (H[h].alive && !(pm[h] + 15 <= 0 && mrel[h] >= 31)) interior = false;
-      if (H[h].alive)
-        cover_b<ALPHA>(H[h].e, L.h[h], S, d - H[h].e.base + 15);
-    }
-    pm_v = hf ? pm[1] : pm[0];
-    mrel_v = hf ? mrel[1] : mrel[0];
-    const int d_blk = d;
-    // the 16 codes entering lanes 0 and 32 during the block
-    uint32_t qw[ALPHA == 0 ? 1 : 4];
-    if constexpr (ALPHA == 0) {
-      qw[0] = Ring<0>::read(rb_l, d - base_l);
-    } else {
-      Ring<1>::read<4>(rb_l, d - base_l, qw);
-    }
-    int st = 0;
+      mpp = fm;
+      ml = xd_writelane_i32((int)(uint32_t)fm, k + 2, ml);
+      mh = xd_writelane_i32((int)(uint32_t)(fm >> 32), k + 2, mh);
+      bool stop = false;
+      if ((k & (G - 1)) == G - 1) {
+        // (on the 32-bit halves: each a window)
+        uint32_t olo = (uint32_t)(mp | fm), ohi = (uint32_t)((mp | fm) >> 32);
+        opaque_s(olo);
+        opaque_s(ohi);
+        if ((live0 && olo == 0) || (live1 && ohi == 0)) stop = true;
+        if ((olo | ohi) >= (1u << (32 - G))) stop = true;  // top G lanes
+      }
+      if constexpr (EDGE) {
+        if ((live0 && k >= rem[0]) || (live1 && k >= rem[1])) stop = true;
+      }
+      return stop;
+    };
     auto run_block = [&](auto edge_tag) {
 #pragma unroll
-      for (int k = 0; k < 16; k += 2) {
-        const int in0 = ALPHA == 0
-            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
-            : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
-        const int in1 = ALPHA == 0
-            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
-            : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
-        st = body(edge_tag, x, y, in0);
-        if (st) { newest_in_y = true; return; }
-        st = body(edge_tag, y, x, in1);
-        if (st) { newest_in_y = false; return; }
-      }
-      newest_in_y = false;
-    };
-    if (interior) run_block(std::false_type{});
-    else run_block(std::true_type{});
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      H[h].e.W += (int64_t)33 * (d - d_blk) - (int64_t)H[h].acc;
-      H[h].acc = 0;
-    }
-    if (!st) continue;
-    // a top lane turned finite: slide that half's window up by the lanes
-    // below its lowest finite cell of d-1 and d-2, or hand the extension on
-    // when not one lane is free
-    int sl[2] = {0, 0};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (!((m1 >> (31 + 32 * h)) & 1)) continue;
-      const int s = __builtin_ctz((uint32_t)((m1 | m2) >> (32 * h)));
-      if (s >= 1) {
-        sl[h] = s;
-      } else {
-        if (lane == 0) {
-          const int slot = atomicAdd(P.counters + C_ESC_TAIL, 1);
-          P.esc_queue[slot] = H[h].item;
+      for (int k = 0; k < KB; k += 2) {
+        if (body(edge_tag, x, y, a1, a2, k)) {
+          nk = k + 1; newest_in_y = true; return;
         }
-        H[h].own = 0;
-        const uint64_t hm = 0xFFFFFFFFull << (32 * h);
-        m1 &= ~hm;
-        m2 &= ~hm;
-        x = hf == h ? NEG : x;
-        y = hf == h ? NEG : y;
+        if (body(edge_tag, y, x, a2, a1, k + 1)) { nk = k + 2; return; }
       }
-    }
-    if (sl[0] | sl[1]) {
-      const int sl_l = hf ? sl[1] : sl[0];
-      const int src = lane + sl_l;
-      const bool in = p + sl_l < 32;
-      const int nw = newest_in_y ? y : x;
-      const int od = newest_in_y ? x : y;
-      const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, nw);
-      const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, od);
-      // target codes move with their cells; stray codes at the top lanes
-      // are not used before they have moved out (see fast_interior)
-      fb = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb);
-      x = in ? pn : NEG;
-      y = in ? po : NEG;
-      newest_in_y = false;
-      m1 = shift_halves(m1, sl[0], sl[1]);
-      m2 = shift_halves(m2, sl[0], sl[1]);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (!sl[h]) continue;
-        H[h].e.base += sl[h];
-        cover_a<ALPHA>(H[h].e, L.h[h], S, H[h].e.base + 30);
-      }
-      base_l = hf ? H[1].e.base : H[0].e.base;
-      fa = code_a(base_l + p - 1);
-    } else if (newest_in_y) {
+    };
+    if (edge) run_block(std::true_type{});
+    else run_block(std::false_type{});
+    if (newest_in_y) {
       const int t = x;
       x = y;
       y = t;
-      newest_in_y = false;
     }
-  }
+    // live-span cells of the block's antidiagonals per window: lane k + 2
+    // forms antidiagonal k's span from the masks of the two before it (lanes
+    // k + 1 and k): lo = ctz(M1 | M2 << 1), hi = 32 - clz(M1 | M2) (M2 never
+    // holds the window's top lane), clamped to the matrix
+    int64_t acc[2];
+    const int kk = lane - 2;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (!H[h].own) continue;
-    ItemResult r;
-    r.status = S_OK;
-    r.cells = H[h].e.W;
-    r.tier = 4; r.pad = 0;
-    if (H[h].bd >= 0) {
-      r.best = H[h].tbest + gap * H[h].bd;
-      r.x = H[h].bxa;
-      r.y = H[h].bd - H[h].bxa;
-    } else {
-      r.best = 0; r.x = 0; r.y = 0;
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t a = (uint32_t)wave_shr1(h ? mh : ml, 0);
+      const uint32_t b = (uint32_t)wave_shr1((int)a, 0);
+      const int lo = max((int)__builtin_ctzg(a | (b << 1), 32), pm[h] + kk);
+      const int hi = min(32 - (int)__builtin_clzg(a | b, 32), mrel[h]);
+      const int cnt = (kk >= 0 && kk < nk && (a | b) != 0) ? max(hi - lo + 1, 0)
+                                                          : 0;
+      acc[h] = sum_lanes(cnt);
     }
-    if (lane == 0) P.items[H[h].item] = r;
+    // ---- after the block: advance and see to each window
+    const uint64_t f1 = ballot(x != NEG), f2 = ballot(y != NEG);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      PairHalf& Hh = H[h];
+      if (Hh.item < 0) continue;
+      PairCold& c = L.c[h];
+      Hh.d += nk;
+      c.W = uni64(c.W) + acc[h];
+      if (bd[h] >= d0[h]) {  // a new best in this block
+        c.bxa = Hh.base + bln[h];
+        c.tbest = tb[h];
+      }
+      Hh.bd = bd[h];
+      Hh.bln = bln[h];
+      Hh.tv0 = tv0s[h] - nk * gap;  // T in the frame of the next antidiagonal
+      Hh.m1 = (uint32_t)(f1 >> (32 * h));
+      Hh.m2 = (uint32_t)(f2 >> (32 * h));
+      const uint32_t o = Hh.m1 | Hh.m2;
+      if (o == 0 || Hh.d > Hh.m + Hh.n) {
+        __builtin_amdgcn_wave_barrier();
+        pair_finish(P, Hh, c, gap);
+        Hh.item = -1;
+        Hh.m1 = Hh.m2 = 0;
+        x = hf == h ? NEG : x;
+        y = hf == h ? NEG : y;
+        continue;
+      }
+      const int cz = (int)__builtin_clz(o);
+      if (cz < G) {
+        // the band reached the top lanes: slide the window up by the lanes
+        // below its lowest finite cell, or hand the extension on
+        const int sl = (int)__builtin_ctz(o);
+        if (cz + sl < G) {
+          if (lane == 0) {
+            const int slot = atomicAdd(P.counters + C_ESC_TAIL, 1);
+            P.esc_queue[slot] = Hh.item;
+          }
+          Hh.item = -1;
+          Hh.m1 = Hh.m2 = 0;
+          x = hf == h ? NEG : x;
+          y = hf == h ? NEG : y;
+          continue;
+        }
+        const int src = lane + sl;
+        const bool inw = p + sl < 32;
+        const int px = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
+        const int py = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y);
+        x = hf == h ? (inw ? px : NEG) : x;
+        y = hf == h ? (inw ? py : NEG) : y;
+        Hh.m1 >>= sl;
+        Hh.m2 >>= sl;
+        Hh.base += sl;
+        int la = uni(c.loaded_a);
+        if (la <= Hh.base + 30) {
+          pair_cover<ALPHA>(L.h[h].ra, S, uni64(c.a_start), uni(c.a_dir), la,
+                            Hh.base + 30);
+          c.loaded_a = la;
+        }
+        __builtin_amdgcn_wave_barrier();
+        load_fa(h);
+      }
+    }
   }
 }
 
-// Persistent pair kernel: pairs of consecutive extensions of the (longest
-// first) order pulled from a device queue.
+// Persistent pair kernel: windows take extensions of the (longest-first)
+// order from the device queue as they become free.
 template <int ALPHA>
 __global__ __launch_bounds__(WAVE * WPB) void xd_pair_kernel(Params P) {
   __shared__ PairLds<ALPHA> lds[WPB];
@@ -1778,27 +1880,8 @@ __global__ __launch_bounds__(WAVE * WPB) void xd_pair_kernel(Params P) {
     __syncthreads();
   }
   const int wid = threadIdx.x >> 6;
-  PairLds<ALPHA>& L = lds[wid];
   const Src S = make_src(P);
-  // pairs of consecutive slots, claimed P.chunk pairs at a time (one device
-  // atomic per claim)
-  int cur = 0, end = 0;
-  for (;;) {
-    if (cur >= end) {
-      int c = 0;
-      if (lane_id() == 0) c = atomicAdd(P.counters + C_PAIR_HEAD, 2 * P.chunk);
-      cur = uni(c);
-      end = min(cur + 2 * P.chunk, P.n_items);
-      if (cur >= P.n_items) break;
-    }
-    const int c = cur;
-    cur += 2;
-    const int i0 = (P.flags & F_ORDERED) ? uni(P.order[c]) : c;
-    int i1 = -1;
-    if (c + 1 < end)
-      i1 = (P.flags & F_ORDERED) ? uni(P.order[c + 1]) : c + 1;
-    run_pair<ALPHA>(P, S, i0, i1, L, tab);
-  }
+  run_pairs<ALPHA>(P, S, lds[wid], tab);
 }
 
 // ------------------------------------------------------------------ dual16

@@ -4,7 +4,7 @@ The library's kernel and host sources are compiled with the host compiler
 against hip/hip_runtime.h of this folder (each GPU thread a fiber, the lanes
 of a wave meeting at every cross-lane operation; see emu_runtime.cpp) into
 ``_build/libxdrop_emu.so``, which exports the same C ABI as libxdrop.so.
-Three textual changes make the kernel source host C++: the GPU intrinsic
+Textual changes make the kernel source host C++: the GPU intrinsic
 name bound to the write-lane declaration is dropped (the runtime defines the
 function), the register-class letters of the empty optimisation-barrier asm
 statements become the host's general class, and the occupancy hint on kernel
@@ -33,7 +33,7 @@ CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 def host_source(text: str) -> str:
     text = re.sub(r'__asm\(\s*"llvm\.amdgcn\.writelane\.i32"\s*\)', "", text)
     text = re.sub(r'"\+[sv]"', '"+r"', text)
-    text = re.sub(r'__attribute__\(\(amdgpu_waves_per_eu\(\d+\)\)\)', "", text)
+    text = re.sub(r'__attribute__\(\(amdgpu_waves_per_eu\([^()]*\)\)\)', "", text)
     # shared variables start with garbage in every block
     def _shared(m):
         names = re.findall(r'(\w+)\s*(?:\[[^\]]*\])?\s*(?:,|$)', m.group(2))

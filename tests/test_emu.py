@@ -228,3 +228,33 @@ def test_dual16_long_extensions(emu):
     g = emu.run(b, product_scoring(s), xdrop.options(variant=5))
     assert not compare(g, oracle_run(b, s))
     assert emu.last_stats()[7] == 8
+
+
+@pytest.mark.parametrize("alphabet,X", [(20, 49), (4, 15), (4, 0), (4, 200)])
+def test_pair_kernel(emu, alphabet, X):
+    """The two-window pair kernel on the CPU build: fuzz batches of related
+    and unrelated pairs; windows refilled from the queue as their extensions
+    end, bands that fill a 32-cell window handed on to the wave kernel
+    (X = 200 makes most of them do so)."""
+    rng = np.random.default_rng([95, alphabet, X])
+    b = make_batch(_fuzz(rng, 60, alphabet, 700), alphabet)
+    s = (inputs.Scheme(4, 2, -3, -2, X) if alphabet == 4 else
+         inputs.Scheme(20, gap=-2, X=X,
+                       matrix=inputs.stand_in_substitution_matrix()))
+    for chunk in (1, 4):
+        g = emu.run(b, product_scoring(s), xdrop.options(variant=4,
+                                                         chunk=chunk))
+        assert not compare(g, oracle_run(b, s)), chunk
+    st = emu.last_stats()
+    assert st[4] > 0, st
+
+
+def test_pair_kernel_long_extensions(emu):
+    """Extensions of 50-100 kb on the pair kernel: ring wrap and many window
+    slides, beside short ones that end early and free their window."""
+    b, s = inputs.workload("dna-tail", 1.0)
+    n = len(b.seeds)
+    b = b.subset([n - 1, n - 2, 0, 1, 2, 3])
+    g = emu.run(b, product_scoring(s), xdrop.options(variant=4))
+    assert not compare(g, oracle_run(b, s))
+    assert emu.last_stats()[4] == 12
