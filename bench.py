@@ -399,9 +399,9 @@ def main():
     plain_ms, _ = time_steps(ctx, dev, sc, res, xdrop.options(variant=3),
                              stream, max(2, args.steps // 2), 1)
     form = ctx.resolve_options(sc, n, opts)
-    # (1) the first extension kernel: the pair kernel in the pair form, else
-    # the wave kernel; (2) the wave kernel on the extensions the pair kernel
-    # handed on
+    # (1) the first extension kernel: the row or 16-bit kernel in those
+    # forms, else the wave kernel; (2) the wave kernel on the extensions
+    # that kernel handed on
     names = ["prep", "extend", "extend_handed_on", "workgroup", "combine"]
     dom = int(np.argmax(phase))
     achieved = OPS_PER_CELL * live / (phase[dom] / 1e3) / 1e12

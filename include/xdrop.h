@@ -114,7 +114,7 @@ enum {
                                     whose band outgrows 32 cells restart on
                                     the wave kernel.  Ignores band_cap (runs
                                     as WAVE when a cap is set) */
-    XDROP_VARIANT_DUAL16 = 5     /* two extensions per wavefront, one in each
+    XDROP_VARIANT_DUAL16 = 5,    /* two extensions per wavefront, one in each
                                     16-bit half of every register (64-cell
                                     windows, packed 16-bit integer
                                     arithmetic on relative scores, paper
@@ -127,6 +127,13 @@ enum {
                                     kernel.  Ignores band_cap (runs as WAVE
                                     when a cap is set).  Results are
                                     bit-exact as on every form */
+    XDROP_VARIANT_ROWS16 = 6     /* four extensions per wavefront (16-cell
+                                    windows, one cell per lane, rows of 16
+                                    lanes); extensions whose band outgrows
+                                    16 cells restart on the wave kernel.
+                                    Suits narrow bands (small X).  Ignores
+                                    band_cap (runs as WAVE when a cap is
+                                    set) */
 };
 typedef struct {
     int32_t variant;      /* XDROP_VARIANT_* */
@@ -254,9 +261,10 @@ int xdrop_extend_batch_graph(xdrop_ctx *ctx, const uint8_t *d_seqs,
  * waits for the last recorded batch, writes to ms[0..n) the durations summed
  * over all batches recorded since timing was switched on or last read --
  * (0) counters, symbol check and longest-first ordering, (1) the first
- * extension kernel (the pair kernel for XDROP_VARIANT_PAIR, else the wave
- * kernel of 1..8 cells per lane), (2) the wave kernel on the extensions the
- * pair kernel handed on (0 for the other variants), (3) the workgroup tier,
+ * extension kernel (the row kernel for XDROP_VARIANT_PAIR and
+ * XDROP_VARIANT_ROWS16, the 16-bit kernel for XDROP_VARIANT_DUAL16, else the
+ * wave kernel of 1..8 cells per lane), (2) the wave kernel on the extensions
+ * the first kernel handed on (0 for the other variants), (3) the workgroup tier,
  * (4) the seed-level combine -- sets *batches (optional) to their number,
  * and starts a new record.  Returns XDROP_E_INVALID if none was recorded. */
 int xdrop_ctx_set_timing(xdrop_ctx *ctx, int32_t on);
@@ -265,10 +273,10 @@ int xdrop_last_timing(xdrop_ctx *ctx, float *ms, int32_t n,
 
 /* Statistics of the last batch on this context (after stream sync):
  * counts of extensions finished at each tile width: counts[0..3] = 1, 2, 4,
- * 8 cells per lane (wave kernel), counts[4] = pair kernel, counts[5] =
+ * 8 cells per lane (wave kernel), counts[4] = two-row (pair) kernel, counts[5] =
  * workgroup (block) tier, bands of 513..2,048 cells, counts[6] =
  * device-memory tier, wider bands, counts[7] = two-extension 16-bit
- * kernel. */
+ * kernel, counts[8] = four-row kernel (XDROP_VARIANT_ROWS16). */
 int xdrop_last_stats(xdrop_ctx *ctx, int64_t *counts, int32_t n_counts);
 
 /* ---------------------------------------------------------------- serving

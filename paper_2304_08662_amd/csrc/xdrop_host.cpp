@@ -63,7 +63,8 @@ struct xdrop_ctx {
   int32_t last_combine_blocks = 0;    // its combine blocks (tier counts)
   char* scratch = nullptr;  // the device's fixed scratch (allocation-free
                             // entry point)
-  int pair_blocks_per_cu[2] = {0, 0};
+  int pair_blocks_per_cu[2] = {0, 0};   // two rows per wave
+  int rows4_blocks_per_cu[2] = {0, 0};  // four rows per wave
   int block_blocks_per_cu[2] = {0, 0};
   int dual_blocks_per_cu[2] = {0, 0};
   int blocks_per_cu[2] = {0, 0};  // [alphabet]
@@ -168,7 +169,7 @@ int fill_scoring(const xdrop_scoring* sc, Params& P) {
 
 int check_options(const xdrop_options* o) {
   if (!o) return XDROP_OK;
-  if (o->variant < 0 || o->variant > XDROP_VARIANT_DUAL16)
+  if (o->variant < 0 || o->variant > XDROP_VARIANT_ROWS16)
     return XDROP_E_INVALID;
   const int t = o->tile;
   if (!(t == 0 || t == 1 || t == 2 || t == 4 || t == 8))
@@ -205,9 +206,10 @@ xdrop_options resolve(const xdrop_ctx* c, const xdrop_scoring* sc,
     r.order = o->order;
     if (o->waves_per_cu) r.waves_per_cu = o->waves_per_cu;
   }
-  // the pair kernel keeps no per-antidiagonal band width: a band cap runs on
+  // the row kernels keep no per-antidiagonal band width: a band cap runs on
   // the wave kernel
-  if ((r.variant == XDROP_VARIANT_PAIR || r.variant == XDROP_VARIANT_DUAL16) &&
+  if ((r.variant == XDROP_VARIANT_PAIR || r.variant == XDROP_VARIANT_DUAL16 ||
+       r.variant == XDROP_VARIANT_ROWS16) &&
       r.band_cap > 0)
     r.variant = XDROP_VARIANT_WAVE;
   if (!r.tile) r.tile = 1;
@@ -380,13 +382,16 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     Q.flags |= F_ESC;
     HIP_OK(launch_wave(Q, persistent_grid(), st));
     if (timed) HIP_OK(hipEventRecord(ev[3], st));
-  } else if (o.variant == XDROP_VARIANT_PAIR) {
-    // two extensions per wave; bands wider than 32 cells are handed on to
-    // the wave kernel
-    const int pairs = (n_items + 1) / 2;
-    const int pgrid = std::min(c->num_cu * c->pair_blocks_per_cu[a],
-                               (pairs + WPB - 1) / WPB);
-    HIP_OK(launch_pair(P, pgrid, st));
+  } else if (o.variant == XDROP_VARIANT_PAIR ||
+             o.variant == XDROP_VARIANT_ROWS16) {
+    // two (four) extensions per wave in rows of 32 (16) lanes; bands that
+    // fill a row are handed on to the wave kernel
+    const int rows = o.variant == XDROP_VARIANT_PAIR ? 2 : 4;
+    const int per_cu = rows == 2 ? c->pair_blocks_per_cu[a]
+                                 : c->rows4_blocks_per_cu[a];
+    const int waves = (n_items + rows - 1) / rows;
+    const int pgrid = std::min(c->num_cu * per_cu, (waves + WPB - 1) / WPB);
+    HIP_OK(launch_rows(P, rows, pgrid, st));
     if (timed) HIP_OK(hipEventRecord(ev[2], st));
     Params Q = P;
     Q.flags |= F_ESC;
@@ -469,7 +474,8 @@ int xdrop_ctx_create(int device, const xdrop_ctx_opts* opts,
   // make no runtime queries, under graph capture or otherwise)
   for (int a = 0; a < 2; ++a) {
     c->blocks_per_cu[a] = wave_blocks_per_cu(a);
-    c->pair_blocks_per_cu[a] = pair_blocks_per_cu(a);
+    c->pair_blocks_per_cu[a] = rows_blocks_per_cu(a, 2);
+    c->rows4_blocks_per_cu[a] = rows_blocks_per_cu(a, 4);
     c->block_blocks_per_cu[a] = block_blocks_per_cu(a);
     c->dual_blocks_per_cu[a] = dual_blocks_per_cu(a);
   }
@@ -742,17 +748,17 @@ extern "C" int xdrop_autotune(xdrop_ctx* c, const uint8_t* d_seqs,
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, hipErrorInvalidDevice);
   hipStream_t st = (hipStream_t)stream;
   const TuneKey key = tune_key(sc, n_seeds);
-  // candidates: the pair form (tile and chunk of the wave kernel that takes
+  // candidates: the row forms (tile and chunk of the wave kernel that takes
   // the extensions it hands on), the persistent wave form (tile x chunk),
   // the plain form (tile), the workgroup form; every field is set, so no
   // tuned entry applies while they are timed
   std::vector<xdrop_options> cand;
   const int tiles[] = {1, 2, 4, 8};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
-  for (int t : {1, 2})
-    for (int ch : {1, 4}) {
+  for (int v : {XDROP_VARIANT_PAIR, XDROP_VARIANT_ROWS16})
+    for (int ch : {4, 16}) {
       xdrop_options o{};
-      o.variant = XDROP_VARIANT_PAIR; o.tile = t; o.chunk = ch;
+      o.variant = v; o.tile = 1; o.chunk = ch;
       cand.push_back(o);
     }
   for (int t : tiles)

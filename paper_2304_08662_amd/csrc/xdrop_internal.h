@@ -29,7 +29,7 @@ constexpr int GEN_CAP = 1 << 16;      // device-memory tier band capacity
 struct ItemResult {
   int32_t best, x, y, status;
   int64_t cells;
-  int32_t tier;  // tier that finished the extension (C_TIER0 order), or -1
+  int32_t tier;  // tier that finished the extension (N_TIERS order)
   int32_t pad;
 };
 
@@ -37,7 +37,7 @@ struct ItemResult {
 enum : int32_t {
   F_PLAIN = 1,      // one wave per extension, no queue
   F_ORDERED = 2,    // items[] holds the processing order
-  F_ESC = 4,        // items come from esc_queue (handed on by the pair kernel)
+  F_ESC = 4,        // items come from esc_queue (handed on by a row or 16-bit kernel)
 };
 
 // Per-seed / per-item status values (mirror the public enum).
@@ -59,7 +59,7 @@ struct Params {
   const uint8_t* seq_bad;    // per-sequence check (BYTE): 2 = bad symbol
   int32_t* gen_queue;        // items handed to the block tier
   int32_t* dev_queue;        // items handed to the device-memory tier
-  int32_t* esc_queue;        // items handed on by the pair kernel
+  int32_t* esc_queue;        // items handed on by the row and 16-bit kernels
   int32_t* gen_scratch;      // device-memory tier rings
   int32_t n_seqs;
   int32_t n_seeds;
@@ -78,10 +78,11 @@ struct Params {
 };
 
 // Extensions finished per tier, in this order: 1, 2, 4, 8 cells per lane
-// (wave kernel), pair kernel, block tier, device-memory tier, two-extension
-// 16-bit kernel.  Each result records its tier; the combine kernel counts
-// them per block (no device-wide atomic per extension).
-constexpr int N_TIERS = 8;
+// (wave kernel), two rows per wave (pair form), block tier, device-memory
+// tier, two-extension 16-bit kernel, four rows per wave.  Each result
+// records its tier; the combine kernel counts them per block (no
+// device-wide atomic per extension).
+constexpr int N_TIERS = 9;
 // Combine blocks of a batch (at most, so that the per-block tier counts fit
 // in the counter block).
 constexpr int MAX_COMBINE_BLOCKS = 2048;
@@ -95,9 +96,9 @@ enum {
   C_HEAD = 0,       // main queue head
   C_GEN_TAIL = 1,   // block tier queue tail
   C_GEN_HEAD = 2,   // block tier queue head
-  C_ESC_TAIL = 3,   // pair kernel hand-on queue tail
+  C_ESC_TAIL = 3,   // hand-on queue tail (row and 16-bit kernels)
   C_ESC_HEAD = 4,   // its head (wave kernel)
-  C_PAIR_HEAD = 5,  // pair kernel queue head
+  C_PAIR_HEAD = 5,  // row and 16-bit kernels: queue head
   C_DEV_TAIL = 6,   // device-memory tier queue tail
   C_DEV_HEAD = 7,   // its head
   C_HIST = 8,       // longest-first ordering: bucket sizes
@@ -129,8 +130,8 @@ hipError_t launch_fill_queue(const int32_t* order, int32_t n, int32_t* queue,
                              int32_t* counters, int32_t tail_slot,
                              hipStream_t s);
 hipError_t launch_wave(const Params& P, int grid, hipStream_t s);
-hipError_t launch_pair(const Params& P, int grid, hipStream_t s);
-int pair_blocks_per_cu(int alphabet);
+hipError_t launch_rows(const Params& P, int rows, int grid, hipStream_t s);
+int rows_blocks_per_cu(int alphabet, int rows);
 hipError_t launch_dual(const Params& P, int grid, hipStream_t s);
 int dual_blocks_per_cu(int alphabet);
 bool dual_exact(const Params& P);  // 16-bit relative scores exact here

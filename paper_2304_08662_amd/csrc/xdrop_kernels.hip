@@ -1419,7 +1419,7 @@ void xd_wave_kernel(Params P) {
           P, S, (P.flags & F_ORDERED) ? uni(P.order[idx]) : idx, w, tab);
     return;
   }
-  // the extensions handed on by the pair kernel, or the whole batch
+  // the extensions handed on by the row or 16-bit kernels, or the whole batch
   const bool esc = (P.flags & F_ESC) != 0;
   const int n_items =
       esc ? uni(__hip_atomic_load(P.counters + C_ESC_TAIL, __ATOMIC_RELAXED,
@@ -1449,116 +1449,158 @@ void xd_wave_kernel(Params P) {
   }
 }
 
-// ------------------------------------------------------------------ pairs
-// Two extensions per wavefront for narrow bands.  Lanes 0-31 run one
-// extension and lanes 32-63 another, one cell per lane, a 32-cell window
-// each (lane 32h + p holds window position p of half h), so every vector
-// instruction of the sweep serves both.  Each half keeps its own
-// antidiagonal, window and scalar state, and takes the next extension from
-// the queue when its own ends.  The sweep is the one-cell loop of the wave
-// kernel on two windows:
-//  * blocks of PKB antidiagonals on finite-lane ballots, whose two 32-bit
-//    halves are the two windows' masks; blocks clear of the matrix edges of
-//    both windows skip the edge masks;
-//  * the top G lanes of each window are -infinity at the start of every
-//    group of G antidiagonals, so the wave rotation brings -infinity to
-//    lanes 0 and 32, and the band is tested against the top every G-th
-//    step; a band that reaches the top slides its window up in place
-//    (`ds_bpermute` within the half);
-//  * thresholds are per lane: a lane compares v - T0 of its window (T in the
-//    frame of the block's first antidiagonal) with constants that move by
-//    -gap per antidiagonal;
-//  * live-span cells are counted per block and window from the masks kept
-//    in lanes of two registers (one per window);
+// ------------------------------------------------------------------ rows
+// Several extensions per wavefront for narrow bands: the 64 lanes form R
+// rows of W = 64 / R lanes (R = 2: 32-cell windows, the pair form; R = 4:
+// 16-lane rows), each row one extension with one cell per lane (lane W*h + p
+// holds window position p of row h), so every vector instruction of the
+// sweep serves R extensions.  Each row keeps its own antidiagonal, window
+// and scalar state, and takes the next extension from the queue when its
+// own ends.  The sweep is the one-cell loop of the wave kernel on R windows:
+//  * blocks of RKB antidiagonals on finite-lane ballots, whose W-bit fields
+//    are the rows' masks; blocks clear of the matrix edges of every row skip
+//    the edge masks;
+//  * the top G lanes of each row are -infinity at the start of every group
+//    of G antidiagonals, so the wave rotation brings -infinity to each row's
+//    lane 0, and the band is tested against the top every G-th step; a band
+//    that reaches the top slides its row's window up in place (`ds_bpermute`
+//    within the row);
+//  * thresholds are per lane: a lane compares v - T0 of its row (T in the
+//    frame of the block's first antidiagonal) with two running scalars that
+//    move by -gap per antidiagonal;
+//  * live-span cells are counted per block and row from the masks kept in
+//    lanes of two registers (the ballot's low and high words);
 //  * byte scores come from per-lane ring reads at immediate offsets, DNA
-//    scores from per-block match words.
-// An extension whose band fills its 32-cell window is handed on to the wave
-// kernel, which restarts it.
-// State of a window's extension that the sweep does not touch between
-// block boundaries; it stays in LDS, so that the block keeps its scalar
-// registers for the sweep.
-struct PairCold {
-  int64_t a_start, b_start, W;  // sources, live-span cells so far
-  int a_dir, b_dir, loaded_a, loaded_b;  // ring levels
-  int bxa, tbest;               // last new best: x and V value
-};
+//    scores from per-block match words;
+//  * the state a block does not touch stays in LDS between blocks, so the
+//    block keeps its scalar registers for the sweep.
+// Each row's sequences stream through rings of their own, half the size of
+// the wave kernel's (a row's window is at most 32 cells).  An extension
+// whose band fills its row (W - G cells) is handed on to the wave kernel,
+// which restarts it.
+
+// Rings of one row: 2,048 DNA codes or 1,024 byte codes.
+template <int ALPHA>
+using RowRing = RingT<ALPHA, ALPHA == 0 ? 2048 : 1024, WAVE>;
 
 template <int ALPHA>
-struct PairLds {
-  WaveLds<ALPHA> h[2];
-  PairCold c[2];
+struct RowWin {
+  uint32_t ra[RowRing<ALPHA>::WORDS];
+  uint32_t rb[RowRing<ALPHA>::WORDS];
 };
 
-// Uniform state of one window's extension kept in scalar registers.
-struct PairHalf {
+// State of a row's extension that the sweep does not touch between block
+// boundaries.
+struct RowCold {
+  int64_t a_start, b_start, W;  // sources, live-span cells so far
+  int a_dir, b_dir, loaded_a, loaded_b;  // ring levels
+  int bd, bxa, tbest;  // last new best: antidiagonal (-1: none), x, V value
+};
+
+template <int ALPHA, int R>
+struct RowLds {
+  RowWin<ALPHA> h[R];
+  RowCold c[R];
+};
+
+// Uniform state of one row's extension kept in scalar registers.
+struct RowHot {
   int item;         // -1: none
   int m, n;         // lengths
   int d, base;      // next antidiagonal, window position 0 = x of base
   int tv0;          // T in the V frame of antidiagonal d
-  int bd, bln;      // last new best: antidiagonal and lane (bd < 0: none)
   uint32_t m1, m2;  // finite lanes of d - 1 and d - 2
 };
 
-// Fills a window's ring up to element need_hi (see cover_a / cover_b).
+// Fills a row's ring up to element need_hi (the ring keeps the RS below).
 template <int ALPHA>
-__device__ __forceinline__ void pair_cover(uint32_t* ring, const Src& S,
-                                           int64_t start, int dir,
-                                           int& loaded, int need_hi) {
+__device__ __forceinline__ void row_cover(uint32_t* ring, const Src& S,
+                                          int64_t start, int dir, int& loaded,
+                                          int need_hi) {
   while (loaded <= need_hi) {
-    Ring<ALPHA>::fill(ring, S, start, dir, loaded, lane_id());
-    loaded += Ring<ALPHA>::CH;
+    RowRing<ALPHA>::fill(ring, S, start, dir, loaded, lane_id());
+    loaded += RowRing<ALPHA>::CH;
   }
   __builtin_amdgcn_wave_barrier();
 }
 
-// Maxima of v over the lanes of each half.
-__device__ __forceinline__ void half_max(int v, int& h0, int& h1) {
+// Every lane: the maximum of v over the lanes of its row (rows of W lanes).
+template <int W>
+__device__ __forceinline__ int row_max_v(int v) {
   v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));
   v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));
   v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));
   v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));
-  h0 = smax(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
-  h1 = smax(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+  // (each 16-lane hardware row now holds its maximum in every lane)
+  if constexpr (W == 16) return v;
+  const int lo = smax(__builtin_amdgcn_readlane(v, 0),
+                      __builtin_amdgcn_readlane(v, 16));
+  const int hi = smax(__builtin_amdgcn_readlane(v, 32),
+                      __builtin_amdgcn_readlane(v, 48));
+  return lane_id() < 32 ? lo : hi;
 }
 
-constexpr int PKB = 48;  // antidiagonals per block of the pair sweep
+// The lane's row's entry of a per-row array.
+template <int R>
+__device__ __forceinline__ int row_sel(const int (&a)[R], int hf) {
+  if constexpr (R == 2) return hf ? a[1] : a[0];
+  return (hf & 2) ? ((hf & 1) ? a[3] : a[2]) : ((hf & 1) ? a[1] : a[0]);
+}
 
-// Result of a finished window's extension.
-__device__ __forceinline__ void pair_finish(const Params& P, const PairHalf& H,
-                                            const PairCold& c, int gap) {
+constexpr int RKB = 48;  // antidiagonals per block of the row sweep
+
+// Result of a finished row's extension (tier: 4 for two rows, 8 for four).
+__device__ __forceinline__ void row_finish(const Params& P, const RowHot& H,
+                                           const RowCold& c, int gap,
+                                           int tier) {
   ItemResult r;
   r.status = S_OK;
   r.cells = uni64(c.W);
-  r.tier = 4; r.pad = 0;
-  if (H.bd >= 0) {
+  r.tier = tier; r.pad = 0;
+  const int bd = uni(c.bd);
+  if (bd >= 0) {
     const int bxa = uni(c.bxa);
-    r.best = uni(c.tbest) + gap * H.bd;
+    r.best = uni(c.tbest) + gap * bd;
     r.x = bxa;
-    r.y = H.bd - bxa;
+    r.y = bd - bxa;
   } else {
     r.best = 0; r.x = 0; r.y = 0;
   }
   if (lane_id() == 0) P.items[H.item] = r;
 }
 
-template <int ALPHA>
-__device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
-                                          PairLds<ALPHA>& L, const int* tab) {
-  constexpr int KB = PKB;
+template <int ALPHA, int R>
+__device__ __forceinline__ void run_rows(const Params& P, const Src& S,
+                                         RowLds<ALPHA, R>& L, const int* tab) {
+  constexpr int W = WAVE / R;
+  constexpr int KB = RKB;
   static_assert(KB % 16 == 0 && KB + 2 <= 64, "match words; mask lanes");
   constexpr int G = 4;
-  constexpr int BIG = 1 << 29;  // T of an idle window: no cell passes
+  constexpr uint32_t RM = (uint32_t)((1ull << W) - 1);  // row bits
+  constexpr int TIER = R == 2 ? 4 : 8;  // result tier index
+  constexpr int BIG = 1 << 29;  // T of an idle row: no cell passes
+  // the top G lanes of every row; the lowest and highest lane of every row
+  constexpr uint64_t TOPS = R == 2 ? 0xF0000000F0000000ull
+                                   : 0xF000F000F000F000ull;
+  constexpr uint64_t LOW1 = R == 2 ? 0x0000000100000001ull
+                                   : 0x0001000100010001ull;
+  constexpr uint64_t HIGH1 = LOW1 << (W - 1);
+  static_assert(R == 2 || R == 4, "rows of 32 or 16 lanes");
+  static_assert(RowRing<ALPHA>::RS >= KB + 34 + RowRing<ALPHA>::CH,
+                "a fill keeps the codes a block still reads");
   const int lane = lane_id();
-  const int hf = lane >> 5, p = lane & 31;
-  const bool in1 = hf != 0;
+  const int hf = lane / W, p = lane % W;
   const int gap = P.gap, X = smin(P.X, 1 << 29);  // see fast_interior
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
-  PairHalf H[2];
-  H[0].item = H[1].item = -1;
-  H[0].m1 = H[0].m2 = H[1].m1 = H[1].m2 = 0;  // (idle windows: no lanes)
-  H[0].d = H[1].d = H[0].base = H[1].base = 0;
-  H[0].m = H[1].m = H[0].n = H[1].n = 0;
-  int x = NEG, y = NEG;  // antidiagonals d-1 and d-2 of the lane's window
+  RowHot H[R];
+#pragma unroll
+  for (int h = 0; h < R; ++h) {
+    H[h].item = -1;
+    H[h].m1 = H[h].m2 = 0;  // (idle rows: no lanes)
+    H[h].d = H[h].base = H[h].m = H[h].n = 0;
+    H[h].tv0 = 0;
+  }
+  int x = NEG, y = NEG;  // antidiagonals d-1 and d-2 of the lane's row
   // DNA: the lane's query code in all 16 code slots of a word; bytes: the
   // byte offset of its score-table row
   uint32_t fa = 0;
@@ -1566,10 +1608,10 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
     const uint32_t* ra = L.h[h].ra;
     uint32_t f;
     if constexpr (ALPHA == 0) {
-      f = (Ring<0>::read(ra, H[h].base + p - 1) & 3u) * 0x55555555u;
+      f = (RowRing<0>::read(ra, H[h].base + p - 1) & 3u) * 0x55555555u;
     } else {
       uint32_t t[1];
-      Ring<1>::read<1>(ra, H[h].base + p - 1, t);
+      RowRing<1>::read<1>(ra, H[h].base + p - 1, t);
       f = (t[0] & 31u) << 7;
     }
     fa = hf == h ? f : fa;
@@ -1581,9 +1623,9 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
   bool drained = false;
   int cur = 0, end = 0;  // queue slots claimed, P.chunk at a time
   for (;;) {
-    // idle windows take the next extensions
+    // idle rows take the next extensions
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < R; ++h) {
       while (H[h].item < 0 && !drained) {
         if (cur >= end) {
           int c = 0;
@@ -1599,103 +1641,116 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
           ItemResult r;
           r.best = 0; r.x = 0; r.y = 0; r.status = st.status;
           r.cells = st.status == S_OK ? 1 : 0;
-          r.tier = st.status == S_OK ? 4 : -1; r.pad = 0;
+          r.tier = st.status == S_OK ? TIER : -1; r.pad = 0;
           if (lane == 0) P.items[item] = r;
           continue;
         }
-        PairHalf& Hh = H[h];
+        RowHot& Hh = H[h];
         Hh.item = item;
         Hh.m = st.e.m; Hh.n = st.e.n;
         Hh.d = 1; Hh.base = 0;
         Hh.tv0 = -gap;  // T = 0 in the frame of antidiagonal 1
-        Hh.bd = -1; Hh.bln = 0;
         Hh.m1 = 1;  // antidiagonal 0: S(0,0) = 0 at window position 0
         Hh.m2 = 0;
         x = hf == h ? (p == 0 ? 0 : NEG) : x;
         y = hf == h ? NEG : y;
         int la = 0;
-        pair_cover<ALPHA>(L.h[h].ra, S, st.e.a_start, st.e.a_dir, la, 30);
-        PairCold& pc = L.c[h];
-        pc.a_start = st.e.a_start; pc.b_start = st.e.b_start; pc.W = 1;
-        pc.a_dir = st.e.a_dir; pc.b_dir = st.e.b_dir;
-        pc.loaded_a = la; pc.loaded_b = 0;
-        pc.bxa = 0; pc.tbest = 0;
+        row_cover<ALPHA>(L.h[h].ra, S, st.e.a_start, st.e.a_dir, la, W - 2);
+        RowCold& rc = L.c[h];
+        rc.a_start = st.e.a_start; rc.b_start = st.e.b_start; rc.W = 1;
+        rc.a_dir = st.e.a_dir; rc.b_dir = st.e.b_dir;
+        rc.loaded_a = la; rc.loaded_b = 0;
+        rc.bd = -1; rc.bxa = 0; rc.tbest = 0;
         __builtin_amdgcn_wave_barrier();
         load_fa(h);
       }
     }
-    const bool live0 = H[0].item >= 0, live1 = H[1].item >= 0;
-    if (!live0 && !live1) break;
+    // idle rows' lanes (all bits of their mask fields)
+    uint64_t idle = 0;
+#pragma unroll
+    for (int h = 0; h < R; ++h)
+      if (H[h].item < 0) idle |= (uint64_t)RM << (W * h);
+    if (idle == ~0ull) break;
 
-    // ---- one block of antidiagonals of both windows
-    int pm[2], mrel[2], rem[2], d0[2], e0[2];
+    // ---- one block of antidiagonals of every row
+    int pm[R], mrel[R], e0[R], tvr[R];
+    int remmin = KB;  // antidiagonals left after d, over the live rows
     bool edge = false;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      PairHalf& Hh = H[h];
+    for (int h = 0; h < R; ++h) {
+      RowHot& Hh = H[h];
       if (Hh.item < 0) {
-        pm[h] = -KB; mrel[h] = 31; rem[h] = KB; d0[h] = 0; e0[h] = 0;
+        pm[h] = -KB; mrel[h] = W - 1; e0[h] = 0;
+        tvr[h] = BIG;
         continue;
       }
-      d0[h] = Hh.d;
       pm[h] = Hh.d - Hh.n - Hh.base;
       mrel[h] = Hh.m - Hh.base;
-      rem[h] = Hh.m + Hh.n - Hh.d;  // antidiagonals left after d
-      if (!(pm[h] + KB - 1 <= 0 && mrel[h] >= 31 && rem[h] >= KB - 1))
+      const int rem = Hh.m + Hh.n - Hh.d;
+      remmin = smin(remmin, rem);
+      tvr[h] = Hh.tv0;
+      if (!(pm[h] + KB - 1 <= 0 && mrel[h] >= W - 1 && rem >= KB - 1))
         edge = true;
       e0[h] = Hh.d - Hh.base;
-      PairCold& c = L.c[h];
-      int lb = uni(c.loaded_b);
+      RowCold& rc = L.c[h];
+      int lb = uni(rc.loaded_b);
       if (lb <= e0[h] + KB - 1) {
-        pair_cover<ALPHA>(L.h[h].rb, S, uni64(c.b_start), uni(c.b_dir), lb,
-                          e0[h] + KB - 1);
-        c.loaded_b = lb;
+        row_cover<ALPHA>(L.h[h].rb, S, uni64(rc.b_start), uni(rc.b_dir), lb,
+                         e0[h] + KB - 1);
+        rc.loaded_b = lb;
       }
     }
-    // per lane: its window's values
-    const int pq = p - (in1 ? pm[1] : pm[0]);  // y <= n from step pq on...
-    const uint64_t in_m = ballot(p <= (in1 ? mrel[1] : mrel[0]));
-    int tv0_v = in1 ? (live1 ? H[1].tv0 : BIG) : (live0 ? H[0].tv0 : BIG);
-    const int e0_l = in1 ? e0[1] : e0[0];
+    // per lane: its row's values
+    const int pq = p - row_sel<R>(pm, hf);  // y <= n from step pq on
+    const uint64_t in_m = ballot(p <= row_sel<R>(mrel, hf));
+    int tv0_v = row_sel<R>(tvr, hf);
+    const int e0_l = row_sel<R>(e0, hf);
     uint32_t mw[KB / 16] = {};  // DNA: match words of the block
-    const uint8_t* cp = reinterpret_cast<const uint8_t*>(in1 ? L.h[1].rb
-                                                              : L.h[0].rb);
+    const uint32_t* rb_l = L.h[0].rb;
+#pragma unroll
+    for (int h = 1; h < R; ++h) rb_l = hf == h ? L.h[h].rb : rb_l;
+    const uint8_t* cp = reinterpret_cast<const uint8_t*>(rb_l);
     int sc_next = 0;
     uint32_t cd1 = 0, cd2 = 0;
     if constexpr (ALPHA == 0) {
-      const uint32_t* rb = in1 ? L.h[1].rb : L.h[0].rb;
 #pragma unroll
       for (int i = 0; i < KB / 16; ++i) {
-        const uint32_t xw = Ring<0>::read(rb, e0_l - p - 1 + 16 * i) ^ fa;
+        const uint32_t xw = RowRing<0>::read(rb_l, e0_l - p - 1 + 16 * i) ^ fa;
         mw[i] = ~(xw | (xw >> 1)) & 0x55555555u;
       }
     } else {
-      cp += (e0_l - p - 1) & (Ring<1>::RS - 1);
+      // (reads up to KB + 2 bytes past a position of the ring, which its
+      // mirror words cover; codes past those covered belong to no step)
+      cp += (e0_l - p - 1) & (RowRing<1>::RS - 1);
       sc_next = score(cp[0]);
       cd1 = cp[1];
       cd2 = cp[2];
     }
-    // finite-lane masks of the block's antidiagonals per window, in lanes of
-    // ml (window 0) and mh (window 1): lanes 0 and 1 the two antidiagonals
-    // before the block, lane k + 2 the k-th
+    // finite-lane masks of the block's antidiagonals, the ballot's low word
+    // in lanes of ml and its high word in lanes of mh: lanes 0 and 1 the two
+    // antidiagonals before the block, lane k + 2 the k-th
+    uint64_t a1 = 0, a2 = 0;
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+      a1 |= (uint64_t)H[h].m1 << (W * h);
+      a2 |= (uint64_t)H[h].m2 << (W * h);
+    }
     int ml = 0, mh = 0;
-    ml = xd_writelane_i32((int)H[0].m2, 0, ml);
-    mh = xd_writelane_i32((int)H[1].m2, 0, mh);
-    ml = xd_writelane_i32((int)H[0].m1, 1, ml);
-    mh = xd_writelane_i32((int)H[1].m1, 1, mh);
-    uint64_t a1 = (uint64_t)H[0].m1 | ((uint64_t)H[1].m1 << 32);
-    uint64_t a2 = (uint64_t)H[0].m2 | ((uint64_t)H[1].m2 << 32);
-    int tv0s[2] = {H[0].tv0, H[1].tv0};
-    int bd[2] = {H[0].bd, H[1].bd}, bln[2] = {H[0].bln, H[1].bln};
-    int tb[2] = {0, 0};  // V value of a new best of this block
+    ml = xd_writelane_i32((int)(uint32_t)a2, 0, ml);
+    mh = xd_writelane_i32((int)(uint32_t)(a2 >> 32), 0, mh);
+    ml = xd_writelane_i32((int)(uint32_t)a1, 1, ml);
+    mh = xd_writelane_i32((int)(uint32_t)(a1 >> 32), 1, mh);
+    // new bests of the block, per lane for its row: step (-1: none), lane,
+    // V value
+    int bk_v = -1, bln_v = 0, tb_v = 0;
     int nk = KB;
     bool newest_in_y = false;
     // running -k * gap and -k * gap - X of step k (set for k = -1)
     uint32_t ck = (uint32_t)gap, thc = (uint32_t)(gap - X);
-    // antidiagonal d_h + k of both windows from prev (d-1, masks mp) and pp
-    // (d-2, masks mpp); pp and mpp receive d.  True when a live window's band
+    // antidiagonal d_h + k of every row from prev (d-1, masks mp) and pp
+    // (d-2, masks mpp); pp and mpp receive d.  True when a live row's band
     // reached its top lanes or had two dead antidiagonals (tested every G),
-    // or at a window's last antidiagonal (edge blocks).
+    // or at a row's last antidiagonal (edge blocks).
     auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
                     uint64_t& mpp, int k) -> bool {
       constexpr bool EDGE = decltype(edge_tag)::value;
@@ -1716,9 +1771,9 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
       int uh = max(up, prev);
       opaque_v(uh);
       const int v = max(uh, dg + sim);
-      // T of the lane's window at this antidiagonal is T0 + ck (ck and the
-      // threshold move by -gap per step: kept as running scalars, which the
-      // compiler would otherwise precompute for every step of the block)
+      // T of the lane's row at this antidiagonal is T0 + ck (ck and the
+      // threshold kept as running scalars, which the compiler would
+      // otherwise precompute for every step of the block)
       ck -= gap;
       thc -= gap;
       opaque_s(ck);
@@ -1734,23 +1789,17 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
       pin_v(vk);
       pp = vk;
       if (__builtin_expect(imp != 0, 0)) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const uint32_t ih = (uint32_t)(imp >> (32 * h));
-          if (!ih) continue;
-          int l0 = __builtin_ctz(ih);
-          int wm = __builtin_amdgcn_readlane(vn, 32 * h + l0);
-          if (__builtin_popcount(ih) > 1) {
-            int a0, b0;
-            half_max(vn, a0, b0);
-            wm = h ? b0 : a0;
-            l0 = __builtin_ctz((uint32_t)(ballot(vn == wm) >> (32 * h)));
-          }
-          tv0s[h] = wm - (int)ck;
-          tv0_v = hf == h ? wm - (int)ck : tv0_v;
-          bd[h] = d0[h] + k;
-          bln[h] = l0;
-          tb[h] = wm;
+        // every row at once: its highest improving cell, the lowest lane
+        // among equals (the rows' improving cells are above all others)
+        const int vi = __builtin_amdgcn_inverse_ballot_w64(imp) ? vn : NEG;
+        const int wm = row_max_v<W>(vi);
+        const uint64_t eq = ballot(vi == wm);
+        const int l0 = __builtin_ctz((uint32_t)(eq >> (W * hf)) | 0x80000000u);
+        if (wm != NEG) {
+          tv0_v = wm - (int)ck;
+          bk_v = k;
+          bln_v = l0;
+          tb_v = wm;
         }
       }
       mpp = fm;
@@ -1758,16 +1807,13 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
       mh = xd_writelane_i32((int)(uint32_t)(fm >> 32), k + 2, mh);
       bool stop = false;
       if ((k & (G - 1)) == G - 1) {
-        // (on the 32-bit halves: each a window)
-        uint32_t olo = (uint32_t)(mp | fm), ohi = (uint32_t)((mp | fm) >> 32);
-        opaque_s(olo);
-        opaque_s(ohi);
-        if ((live0 && olo == 0) || (live1 && ohi == 0)) stop = true;
-        if ((olo | ohi) >= (1u << (32 - G))) stop = true;  // top G lanes
+        // a live row with no finite lane in the two antidiagonals (a zero
+        // W-bit field of o, idle rows filled), or finite top lanes
+        const uint64_t o = mp | fm, oi = o | idle;
+        if ((((oi - LOW1) & ~oi & HIGH1) | (o & TOPS)) != 0) stop = true;
       }
-      if constexpr (EDGE) {
-        if ((live0 && k >= rem[0]) || (live1 && k >= rem[1])) stop = true;
-      }
+      if constexpr (EDGE)
+        if (k >= remmin) stop = true;
       return stop;
     };
     auto run_block = [&](auto edge_tag) {
@@ -1786,51 +1832,62 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
       x = y;
       y = t;
     }
-    // live-span cells of the block's antidiagonals per window: lane k + 2
+    // live-span cells of the block's antidiagonals per row: lane k + 2
     // forms antidiagonal k's span from the masks of the two before it (lanes
-    // k + 1 and k): lo = ctz(M1 | M2 << 1), hi = 32 - clz(M1 | M2) (M2 never
-    // holds the window's top lane), clamped to the matrix
-    int64_t acc[2];
+    // k + 1 and k): lo = ctz(M1 | M2 << 1), hi = index of the top bit of
+    // M1 | M2, plus 1 (M2 never holds the row's top lane), clamped to the
+    // matrix
+    const uint32_t al = (uint32_t)wave_shr1(ml, 0), ah = (uint32_t)wave_shr1(mh, 0);
+    const uint32_t bl = (uint32_t)wave_shr1((int)al, 0), bh = (uint32_t)wave_shr1((int)ah, 0);
     const int kk = lane - 2;
+    int64_t acc[R];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t a = (uint32_t)wave_shr1(h ? mh : ml, 0);
-      const uint32_t b = (uint32_t)wave_shr1((int)a, 0);
+    for (int h = 0; h < R; ++h) {
+      if (H[h].item >= 0) {  // (recomputed: not kept over the block)
+        uint32_t dh = (uint32_t)H[h].d;
+        opaque_s(dh);
+        pm[h] = (int)dh - H[h].n - H[h].base;
+        mrel[h] = H[h].m - H[h].base;
+      }
+      const int sh = (h * W) & 31;
+      const uint32_t a = ((h * W < 32 ? al : ah) >> sh) & RM;
+      const uint32_t b = ((h * W < 32 ? bl : bh) >> sh) & RM;
       const int lo = max((int)__builtin_ctzg(a | (b << 1), 32), pm[h] + kk);
       const int hi = min(32 - (int)__builtin_clzg(a | b, 32), mrel[h]);
       const int cnt = (kk >= 0 && kk < nk && (a | b) != 0) ? max(hi - lo + 1, 0)
                                                           : 0;
       acc[h] = sum_lanes(cnt);
     }
-    // ---- after the block: advance and see to each window
+    // ---- after the block: advance and see to each row
     const uint64_t f1 = ballot(x != NEG), f2 = ballot(y != NEG);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      PairHalf& Hh = H[h];
+    for (int h = 0; h < R; ++h) {
+      RowHot& Hh = H[h];
       if (Hh.item < 0) continue;
-      PairCold& c = L.c[h];
-      Hh.d += nk;
-      c.W = uni64(c.W) + acc[h];
-      if (bd[h] >= d0[h]) {  // a new best in this block
-        c.bxa = Hh.base + bln[h];
-        c.tbest = tb[h];
+      RowCold& rc = L.c[h];
+      const int bk = __builtin_amdgcn_readlane(bk_v, W * h);
+      if (bk >= 0) {  // a new best in this block
+        rc.bd = Hh.d + bk;
+        rc.bxa = Hh.base + __builtin_amdgcn_readlane(bln_v, W * h);
+        rc.tbest = __builtin_amdgcn_readlane(tb_v, W * h);
       }
-      Hh.bd = bd[h];
-      Hh.bln = bln[h];
-      Hh.tv0 = tv0s[h] - nk * gap;  // T in the frame of the next antidiagonal
-      Hh.m1 = (uint32_t)(f1 >> (32 * h));
-      Hh.m2 = (uint32_t)(f2 >> (32 * h));
+      Hh.d += nk;
+      rc.W = uni64(rc.W) + acc[h];
+      // T in the frame of the next antidiagonal
+      Hh.tv0 = __builtin_amdgcn_readlane(tv0_v, W * h) - nk * gap;
+      Hh.m1 = (uint32_t)(f1 >> (W * h)) & RM;
+      Hh.m2 = (uint32_t)(f2 >> (W * h)) & RM;
       const uint32_t o = Hh.m1 | Hh.m2;
       if (o == 0 || Hh.d > Hh.m + Hh.n) {
         __builtin_amdgcn_wave_barrier();
-        pair_finish(P, Hh, c, gap);
+        row_finish(P, Hh, rc, gap, TIER);
         Hh.item = -1;
         Hh.m1 = Hh.m2 = 0;
         x = hf == h ? NEG : x;
         y = hf == h ? NEG : y;
         continue;
       }
-      const int cz = (int)__builtin_clz(o);
+      const int cz = (int)__builtin_clz(o) - (32 - W);  // free lanes on top
       if (cz < G) {
         // the band reached the top lanes: slide the window up by the lanes
         // below its lowest finite cell, or hand the extension on
@@ -1847,7 +1904,7 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
           continue;
         }
         const int src = lane + sl;
-        const bool inw = p + sl < 32;
+        const bool inw = p + sl < W;
         const int px = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
         const int py = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y);
         x = hf == h ? (inw ? px : NEG) : x;
@@ -1855,11 +1912,11 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
         Hh.m1 >>= sl;
         Hh.m2 >>= sl;
         Hh.base += sl;
-        int la = uni(c.loaded_a);
-        if (la <= Hh.base + 30) {
-          pair_cover<ALPHA>(L.h[h].ra, S, uni64(c.a_start), uni(c.a_dir), la,
-                            Hh.base + 30);
-          c.loaded_a = la;
+        int la = uni(rc.loaded_a);
+        if (la <= Hh.base + W - 2) {
+          row_cover<ALPHA>(L.h[h].ra, S, uni64(rc.a_start), uni(rc.a_dir), la,
+                           Hh.base + W - 2);
+          rc.loaded_a = la;
         }
         __builtin_amdgcn_wave_barrier();
         load_fa(h);
@@ -1868,11 +1925,11 @@ __device__ __forceinline__ void run_pairs(const Params& P, const Src& S,
   }
 }
 
-// Persistent pair kernel: windows take extensions of the (longest-first)
-// order from the device queue as they become free.
-template <int ALPHA>
-__global__ __launch_bounds__(WAVE * WPB) void xd_pair_kernel(Params P) {
-  __shared__ PairLds<ALPHA> lds[WPB];
+// Persistent row kernel: R rows per wave take extensions of the
+// (longest-first) order from the device queue as they become free.
+template <int ALPHA, int R>
+__global__ __launch_bounds__(WAVE * WPB) void xd_rows_kernel(Params P) {
+  __shared__ RowLds<ALPHA, R> lds[WPB];
   __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
   if constexpr (ALPHA == 1) {
     for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
@@ -1881,7 +1938,7 @@ __global__ __launch_bounds__(WAVE * WPB) void xd_pair_kernel(Params P) {
   }
   const int wid = threadIdx.x >> 6;
   const Src S = make_src(P);
-  run_pairs<ALPHA>(P, S, lds[wid], tab);
+  run_rows<ALPHA, R>(P, S, lds[wid], tab);
 }
 
 // ------------------------------------------------------------------ dual16
@@ -3072,8 +3129,10 @@ __global__ __launch_bounds__(256) void xd_combine_kernel(Params P, void* out_v) 
 
 template __global__ void xd_wave_kernel<0, 8>(Params);
 template __global__ void xd_wave_kernel<1, 8>(Params);
-template __global__ void xd_pair_kernel<0>(Params);
-template __global__ void xd_pair_kernel<1>(Params);
+template __global__ void xd_rows_kernel<0, 2>(Params);
+template __global__ void xd_rows_kernel<1, 2>(Params);
+template __global__ void xd_rows_kernel<0, 4>(Params);
+template __global__ void xd_rows_kernel<1, 4>(Params);
 template __global__ void xd_block_kernel<0>(Params);
 template __global__ void xd_block_kernel<1>(Params);
 template __global__ void xd_dual_kernel<0>(Params);
@@ -3169,25 +3228,32 @@ hipError_t launch_wave(const Params& P, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pair(const Params& P, int grid, hipStream_t s) {
+hipError_t launch_rows(const Params& P, int rows, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (P.alphabet == 0)
-    hipLaunchKernelGGL((xd_pair_kernel<0>), dim3(grid), dim3(WAVE * WPB), 0,
-                       s, P);
-  else
-    hipLaunchKernelGGL((xd_pair_kernel<1>), dim3(grid), dim3(WAVE * WPB), 0,
-                       s, P);
+  const dim3 g(grid), b(WAVE * WPB);
+  if (rows == 2) {
+    if (P.alphabet == 0) hipLaunchKernelGGL((xd_rows_kernel<0, 2>), g, b, 0, s, P);
+    else hipLaunchKernelGGL((xd_rows_kernel<1, 2>), g, b, 0, s, P);
+  } else {
+    if (P.alphabet == 0) hipLaunchKernelGGL((xd_rows_kernel<0, 4>), g, b, 0, s, P);
+    else hipLaunchKernelGGL((xd_rows_kernel<1, 4>), g, b, 0, s, P);
+  }
   return hipGetLastError();
 }
 
-int pair_blocks_per_cu(int alphabet) {
+int rows_blocks_per_cu(int alphabet, int rows) {
   int nb = 0;
-  hipError_t e =
-      alphabet == 0
-          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &nb, xd_pair_kernel<0>, WAVE * WPB, 0)
-          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &nb, xd_pair_kernel<1>, WAVE * WPB, 0);
+  hipError_t e;
+  if (rows == 2)
+    e = alphabet == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, xd_rows_kernel<0, 2>, WAVE * WPB, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, xd_rows_kernel<1, 2>, WAVE * WPB, 0);
+  else
+    e = alphabet == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, xd_rows_kernel<0, 4>, WAVE * WPB, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, xd_rows_kernel<1, 4>, WAVE * WPB, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

@@ -38,6 +38,7 @@ VARIANT_WORKGROUP = 2
 VARIANT_PLAIN = 3
 VARIANT_PAIR = 4
 VARIANT_DUAL16 = 5
+VARIANT_ROWS16 = 6
 
 SEED_DTYPE = np.dtype([("q", "<i4"), ("t", "<i4"), ("q_pos", "<i4"),
                        ("t_pos", "<i4"), ("k", "<i4")])
@@ -314,9 +315,9 @@ class Context:
     def last_stats(self) -> list:
         """Extensions finished per tier: 1, 2, 4, 8 cells per lane, pair
         kernel, block tier, device-memory tier, two-extension 16-bit
-        kernel."""
-        arr = (ctypes.c_int64 * 8)()
-        _check(self.lib.xdrop_last_stats(self.handle, arr, 8),
+        kernel, four-row kernel."""
+        arr = (ctypes.c_int64 * 9)()
+        _check(self.lib.xdrop_last_stats(self.handle, arr, 9),
                "xdrop_last_stats")
         return list(arr)
 

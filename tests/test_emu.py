@@ -230,31 +230,36 @@ def test_dual16_long_extensions(emu):
     assert emu.last_stats()[7] == 8
 
 
+@pytest.mark.parametrize("variant,tier", [(4, 4), (6, 8)])
 @pytest.mark.parametrize("alphabet,X", [(20, 49), (4, 15), (4, 0), (4, 200)])
-def test_pair_kernel(emu, alphabet, X):
-    """The two-window pair kernel on the CPU build: fuzz batches of related
-    and unrelated pairs; windows refilled from the queue as their extensions
-    end, bands that fill a 32-cell window handed on to the wave kernel
-    (X = 200 makes most of them do so)."""
+def test_row_kernels(emu, alphabet, X, variant, tier):
+    """The row kernels on the CPU build (two rows of 32 lanes, four rows of
+    16 lanes per wave): fuzz batches of related and unrelated pairs; rows
+    refilled from the queue as their extensions end, bands that fill a row
+    handed on to the wave kernel (X = 200 makes most of them do so)."""
     rng = np.random.default_rng([95, alphabet, X])
     b = make_batch(_fuzz(rng, 60, alphabet, 700), alphabet)
     s = (inputs.Scheme(4, 2, -3, -2, X) if alphabet == 4 else
          inputs.Scheme(20, gap=-2, X=X,
                        matrix=inputs.stand_in_substitution_matrix()))
     for chunk in (1, 4):
-        g = emu.run(b, product_scoring(s), xdrop.options(variant=4,
+        g = emu.run(b, product_scoring(s), xdrop.options(variant=variant,
                                                          chunk=chunk))
         assert not compare(g, oracle_run(b, s)), chunk
-    st = emu.last_stats()
-    assert st[4] > 0, st
+        st = emu.last_stats()
+        assert sum(st) == 2 * len(b.seeds), st
+    assert st[tier] > 0, st
 
 
-def test_pair_kernel_long_extensions(emu):
-    """Extensions of 50-100 kb on the pair kernel: ring wrap and many window
-    slides, beside short ones that end early and free their window."""
+@pytest.mark.parametrize("variant,tier,X", [(4, 4, 15), (6, 8, 6)])
+def test_row_kernels_long_extensions(emu, variant, tier, X):
+    """Extensions of 50-100 kb on the row kernels: ring wrap and many window
+    slides, beside short ones that end early and free their row (X = 6 keeps
+    the bands of the long extensions within 16-lane rows)."""
     b, s = inputs.workload("dna-tail", 1.0)
+    s = inputs.Scheme(4, s.match, s.mismatch, s.gap, X)
     n = len(b.seeds)
     b = b.subset([n - 1, n - 2, 0, 1, 2, 3])
-    g = emu.run(b, product_scoring(s), xdrop.options(variant=4))
+    g = emu.run(b, product_scoring(s), xdrop.options(variant=variant))
     assert not compare(g, oracle_run(b, s))
-    assert emu.last_stats()[4] == 12
+    assert emu.last_stats()[tier] == 12

@@ -171,17 +171,20 @@ def test_variants_identical(runner):
     for v, tile, chunk, order in [(1, 1, 1, 0), (1, 2, 3, 0), (1, 4, 8, 1),
                                   (1, 8, 64, 0), (3, 1, 1, 0), (3, 8, 1, 1),
                                   (2, 1, 1, 0), (4, 1, 1, 0), (4, 2, 4, 1),
-                                  (4, 8, 1, 0), (5, 1, 1, 0), (5, 1, 1, 1)]:
+                                  (4, 8, 1, 0), (5, 1, 1, 0), (5, 1, 1, 1),
+                                  (6, 1, 1, 0), (6, 1, 16, 1)]:
         o = xdrop.options(v, tile, chunk, 0, order)
         g = runner.run(batch, scheme, o, dev=dev)
         bad = compare(g, ref)
         assert not bad, ((v, tile, chunk, order), bad[:5])
 
 
-def test_pair_kernel_hands_on_wide_bands(runner):
-    """The pair form: narrow extensions finish in the pair kernel,
-    extensions whose band outgrows 32 cells restart on the wave kernel; the
-    results equal the oracle's either way."""
+@pytest.mark.parametrize("variant,tier", [(4, 4), (6, 8)])
+def test_row_kernels_hand_on_wide_bands(runner, variant, tier):
+    """The row forms (two rows of 32 lanes, four rows of 16 per wave):
+    narrow extensions finish in the row kernel, extensions whose band fills
+    a row restart on the wave kernel; the results equal the oracle's either
+    way."""
     from paper_2304_08662_amd import xdrop
     rng = np.random.default_rng(28)
     pairs = _fuzz_pairs(rng, 120, 4, 700, related_p=0.7)
@@ -190,12 +193,12 @@ def test_pair_kernel_hands_on_wide_bands(runner):
     for X in (8, 60, 2**31 - 1):
         scheme = inputs.Scheme(4, 1, -1, -1, X)
         ref = oracle_run(batch, scheme)
-        g = runner.run(batch, scheme, xdrop.options(variant=4))
+        g = runner.run(batch, scheme, xdrop.options(variant=variant))
         assert not compare(g, ref), X
         stats = runner.ctx.last_stats()
         assert sum(stats) == 2 * len(batch.seeds), stats
         if X == 8:
-            assert stats[4] > 0, stats
+            assert stats[tier] > 0, stats
 
 
 def test_wide_bands_all_tiers(runner):
@@ -384,7 +387,7 @@ def test_invalid_arguments(runner):
     with pytest.raises(xdrop.XdropError):
         runner.run(batch, inputs.Scheme(4, 1, -1, -1, -1))
     with pytest.raises(xdrop.XdropError):
-        runner.run(batch, inputs.Scheme(4, 1, -1, -1, 5), xdrop.options(variant=6))
+        runner.run(batch, inputs.Scheme(4, 1, -1, -1, 5), xdrop.options(variant=7))
 
 
 def test_graph_replay(runner):

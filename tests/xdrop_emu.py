@@ -68,6 +68,6 @@ class EmuLib:
         return res[:n]
 
     def last_stats(self):
-        arr = (ctypes.c_int64 * 8)()
-        assert self.lib.xdrop_last_stats(self.ctx, arr, 8) == 0
+        arr = (ctypes.c_int64 * 9)()
+        assert self.lib.xdrop_last_stats(self.ctx, arr, 9) == 0
         return list(arr)
