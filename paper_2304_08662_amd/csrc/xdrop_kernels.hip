@@ -50,6 +50,19 @@ namespace xd {
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// The LDS copy of the byte-code score table has rows of TAB_LD words (33):
+// with rows of 32, the bank of entry (q, c) would be fixed by the target code
+// c alone, so lanes reading different rows at one code would meet in a bank;
+// the odd stride spreads (q, c) over the banks.
+constexpr int TAB_LD = TABLE_DIM + 1;
+constexpr int TAB_WORDS = TABLE_DIM * TAB_LD;
+__device__ __forceinline__ void fill_tab(int* tab, const Params& P) {
+  for (int i = threadIdx.x; i < TAB_WORDS; i += blockDim.x) {
+    const int q = i / TAB_LD, c = i - q * TAB_LD;
+    tab[i] = c < TABLE_DIM ? P.table[q * TABLE_DIM + c] : 0;
+  }
+}
+
 // Hide a value's origin from the optimiser (no instruction is emitted), so
 // that it cannot turn the operations that follow into longer forms: a
 // scalar (s) or vector (v) register.
@@ -389,7 +402,7 @@ struct Syms<1, C> {
     Ring<1>::read<NB>(w.ra, base + lane_id() * C - 1, v);
 #pragma unroll
     for (int j = 0; j < C; ++j)
-      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) << 5;
+      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) * TAB_LD;
   }
   __device__ void load_b(const WaveLds<1>& w, int d, int base) {
     const int yb = d - base - lane_id() * C - 1;
@@ -667,7 +680,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     } else {
       uint32_t t[1];
       Ring<1>::read<1>(w.ra, base + lane - 1, t);
-      fa = (t[0] & 31u) << 7;
+      fa = (t[0] & 31u) * (4 * TAB_LD);
     }
   };
   // bytes: score of the lane's cell for target code c
@@ -732,7 +745,11 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       sim = sc_next;
       sc_next = score(cd1);
       cd1 = cd2;
-      cd2 = cp[k + 3];
+      // (the load's zero extension stays with it: left to the block after
+      // the improvement branch, it becomes a separate mask there)
+      int c3 = cp[k + 3];
+      opaque_v(c3);
+      cd2 = (uint32_t)c3;
     }
     // (every lane of a wave rotation has a source, so bound_ctrl changes
     // nothing; it lets the compiler fold the move into its user, a VOP2
@@ -965,7 +982,7 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       Ring<1>::read<1>(w.ra, sa, ta);
 #pragma unroll
       for (int j = 0; j < C; ++j)
-        fa[j] = (int)((ta[0] >> (8 * j)) & 31u) << 5;
+        fa[j] = (int)((ta[0] >> (8 * j)) & 31u) * TAB_LD;
     }
   };
   load_fa();
@@ -1403,10 +1420,9 @@ __global__ __launch_bounds__(WAVE * WPB) __attribute__((amdgpu_waves_per_eu(ALPH
 void xd_wave_kernel(Params P) {
   constexpr int CMIN = 1;
   __shared__ WaveLds<ALPHA> lds[WPB];
-  __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
+  __shared__ int tab[ALPHA == 1 ? TAB_WORDS : 1];
   if constexpr (ALPHA == 1) {
-    for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
-      tab[i] = P.table[i];
+    fill_tab(tab, P);
     __syncthreads();
   }
   const int wid = threadIdx.x >> 6;
@@ -1543,8 +1559,10 @@ __device__ __forceinline__ int row_max_v(int v) {
 // The lane's row's entry of a per-row array.
 template <int R>
 __device__ __forceinline__ int row_sel(const int (&a)[R], int hf) {
-  if constexpr (R == 2) return hf ? a[1] : a[0];
-  return (hf & 2) ? ((hf & 1) ? a[3] : a[2]) : ((hf & 1) ? a[1] : a[0]);
+  if constexpr (R == 2)
+    return hf ? a[1] : a[0];
+  else
+    return (hf & 2) ? ((hf & 1) ? a[3] : a[2]) : ((hf & 1) ? a[1] : a[0]);
 }
 
 constexpr int RKB = 48;  // antidiagonals per block of the row sweep
@@ -1612,7 +1630,7 @@ __device__ __forceinline__ void run_rows(const Params& P, const Src& S,
     } else {
       uint32_t t[1];
       RowRing<1>::read<1>(ra, H[h].base + p - 1, t);
-      f = (t[0] & 31u) << 7;
+      f = (t[0] & 31u) * (4 * TAB_LD);
     }
     fa = hf == h ? f : fa;
   };
@@ -1764,7 +1782,9 @@ __device__ __forceinline__ void run_rows(const Params& P, const Src& S,
         sim = sc_next;
         sc_next = score(cd1);
         cd1 = cd2;
-        cd2 = cp[k + 3];
+        int c3 = cp[k + 3];  // (zero extension kept with the load)
+        opaque_v(c3);
+        cd2 = (uint32_t)c3;
       }
       const int up = __builtin_amdgcn_update_dpp(0, prev, 0x13C, 0xf, 0xf, true);
       const int dg = __builtin_amdgcn_update_dpp(0, pp, 0x13C, 0xf, 0xf, true);
@@ -1930,10 +1950,9 @@ __device__ __forceinline__ void run_rows(const Params& P, const Src& S,
 template <int ALPHA, int R>
 __global__ __launch_bounds__(WAVE * WPB) void xd_rows_kernel(Params P) {
   __shared__ RowLds<ALPHA, R> lds[WPB];
-  __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
+  __shared__ int tab[ALPHA == 1 ? TAB_WORDS : 1];
   if constexpr (ALPHA == 1) {
-    for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
-      tab[i] = P.table[i];
+    fill_tab(tab, P);
     __syncthreads();
   }
   const int wid = threadIdx.x >> 6;
@@ -2486,13 +2505,13 @@ struct BCodes<0, C> {
 template <int C>
 struct BCodes<1, C> {
   static constexpr int NB = (C + 3) / 4;
-  int row[C];  // 32 * query code
+  int row[C];  // TAB_LD * query code
   __device__ void load(const uint32_t* ra, int base) {
     uint32_t v[NB];
     BRing<1>::read<NB>(ra, base + (int)threadIdx.x * C - 1, v);
 #pragma unroll
     for (int j = 0; j < C; ++j)
-      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) << 5;
+      row[j] = (int)((v[j >> 2] >> (8 * (j & 3))) & 31u) * TAB_LD;
   }
   __device__ void sims(const uint32_t* rb, int yb, const Params&,
                        const int* tab, int (&s)[C]) const {
@@ -2755,11 +2774,8 @@ __device__ __forceinline__ void run_bitem(const Params& P, const Src& S,
 template <int ALPHA>
 __global__ __launch_bounds__(BT_NT) void xd_block_kernel(Params P) {
   __shared__ BlockLds<ALPHA> L;
-  __shared__ int tab[ALPHA == 1 ? TABLE_DIM * TABLE_DIM : 1];
-  if constexpr (ALPHA == 1) {
-    for (int i = threadIdx.x; i < TABLE_DIM * TABLE_DIM; i += blockDim.x)
-      tab[i] = P.table[i];
-  }
+  __shared__ int tab[ALPHA == 1 ? TAB_WORDS : 1];
+  if constexpr (ALPHA == 1) fill_tab(tab, P);
   const Src S = make_src(P);
   const int tail = P.counters[C_GEN_TAIL];  // final: set by earlier kernels
   for (;;) {
