@@ -1484,6 +1484,14 @@ void xd_wave_kernel(Params P) {
 //  * thresholds are per lane: a lane compares v - T0 of its row (T in the
 //    frame of the block's first antidiagonal) with two running scalars that
 //    move by -gap per antidiagonal;
+//  * a new best is found for every row at once: each lane takes the
+//    maximum of its row's improving cells (DPP maxima within the row) and
+//    the lowest lane among equals from one ballot, and keeps step, lane and
+//    value for its row in three registers until the block ends (per-row
+//    scalar bookkeeping in the steps had spilled the scalar registers);
+//  * the test of every fourth step is one check over the 64-bit mask: a
+//    live row with no finite lane in the last two antidiagonals (a zero
+//    W-bit field, idle rows filled with ones) or a finite top lane;
 //  * live-span cells are counted per block and row from the masks kept in
 //    lanes of two registers (the ballot's low and high words);
 //  * byte scores come from per-lane ring reads at immediate offsets, DNA
