@@ -347,7 +347,8 @@ int enqueue(xdrop_ctx* c, const uint8_t* d_seqs, const int64_t* d_offsets,
     P.seq_bad = (const uint8_t*)(ws + L.bad);
     HIP_OK(launch_validate(d_seqs, d_offsets, n_seqs, P.seeds, n_seeds,
                            sc->alphabet_size, (uint8_t*)(ws + L.bad),
-                           std::min(c->num_cu * 8, (n_seqs + 3) / 4 + 1), st));
+                           std::min(c->num_cu * 64, (n_seqs + 15) / 16 + 1),
+                           st));
   }
   if (o.order == 0 && !plain) {
     int32_t* ord = (int32_t*)(ws + L.order);

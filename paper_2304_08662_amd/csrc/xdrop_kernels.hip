@@ -2947,48 +2947,67 @@ __global__ void xd_mark_kernel(const int32_t* seeds, int32_t n_seeds,
   if (t >= 0 && t < n_seqs) state[t] = 1;
 }
 
+// Bytes of the 32-bit word w at or above asize (asize <= 32): one 0x80 per
+// such byte.  (b & 0x7F) + 0x80 - asize reaches 0x80 exactly when the low
+// seven bits are >= asize and cannot carry into the next byte; b's own top
+// bit covers codes of 128 and more.
+__device__ __forceinline__ uint32_t bytes_at_least(uint32_t w, uint32_t k) {
+  return (((w & 0x7F7F7F7Fu) + k) | w) & 0x80808080u;
+}
+// 0x80 in bytes lo .. hi-1 of a word (0 <= lo, hi <= 4).
+__device__ __forceinline__ uint32_t byte_span_mask(int lo, int hi) {
+  if (hi <= lo) return 0u;
+  return (0xFFFFFFFFu >> (8 * (4 - hi))) & (0xFFFFFFFFu << (8 * lo)) &
+         0x80808080u;
+}
+
 __global__ void xd_validate_kernel(const uint8_t* seqs, const int64_t* offsets,
                                    int32_t n_seqs, int32_t asize,
                                    uint8_t* state) {
-  // four sequences per wave, 16 lanes each, 8-byte loads (the stream is
-  // read in whole words, as the extension kernels read it); the state and
-  // offsets of a sequence are loaded together
+  // four sequences per wave, 16 lanes each; a group reads its sequence in
+  // 16-byte pieces, 256 bytes per round (the stream is read in whole words,
+  // as the extension kernels read it, so the last piece may hold bytes of
+  // the next sequence or past the stream end: they are masked); every byte
+  // is tested against the alphabet on the whole word at once
   const int lane = lane_id();
   const int g = lane >> 4, gl = lane & 15;
   const int wpb = blockDim.x >> 6;
   const int64_t wave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * wpb;
   const uint32_t* words = (const uint32_t*)seqs;
-  const uint2* pairs = (const uint2*)seqs;
-  // 8-byte pairs of words whose second word still holds stream bytes (the
-  // stream is read in whole words only)
-  const int64_t tw = (offsets[n_seqs] + 3) >> 2;
-  const bool al8 = ((uintptr_t)seqs & 7) == 0;
+  const uint4* quads = (const uint4*)seqs;
+  const int64_t tw = (offsets[n_seqs] + 3) >> 2;  // words of the stream
+  const bool al16 = ((uintptr_t)seqs & 15) == 0;
+  const uint32_t k = (uint32_t)(0x80 - asize) * 0x01010101u;
   for (int64_t s0 = wave * 4; s0 < n_seqs; s0 += nwaves * 4) {
     const int64_t s = s0 + g;
-    int found = 0;
-    if (s < n_seqs) {
-      const int st = state[s];
+    uint32_t found = 0;
+    if (s < n_seqs && state[s] == 1) {
       const int64_t a = offsets[s], b = offsets[s + 1];
-      if (st == 1 && b > a) {
-        const int64_t pend = (b - 1) >> 3;
-#pragma unroll 2
-        for (int64_t pi = (a >> 3) + gl; pi <= pend; pi += 16) {
-          uint32_t v[2];
-          if (al8 && 2 * pi + 1 < tw) {
-            const uint2 q = pairs[pi];
-            v[0] = q.x;
-            v[1] = q.y;
+      if (b > a) {
+        const int64_t qend = (b - 1) >> 4;
+        for (int64_t qi = (a >> 4) + gl; qi <= qend; qi += 16) {
+          uint32_t v[4];
+          if (al16 && 4 * qi + 3 < tw) {
+            const uint4 q = quads[qi];
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
           } else {
-            v[0] = words[2 * pi];
-            // (2 pi + 1 past the stream: none of its bytes is checked)
-            v[1] = 2 * pi + 1 < tw ? words[2 * pi + 1] : 0;
-          }
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int64_t p = pi * 8 + i;
-            found |= (p >= a && p < b &&
-                      ((v[i >> 2] >> (8 * (i & 3))) & 0xFFu) >= (uint32_t)asize);
+            for (int i = 0; i < 4; ++i)
+              v[i] = 4 * qi + i < tw ? words[4 * qi + i] : 0u;
+          }
+          const int64_t pb = qi * 16;  // byte position of v[0]'s first byte
+          const bool whole = pb >= a && pb + 16 <= b;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            uint32_t bad = bytes_at_least(v[i], k);
+            if (!whole) {
+              const int64_t wb = pb + 4 * i;
+              const int lo = (int)(a > wb ? (a - wb < 4 ? a - wb : 4) : 0);
+              const int hi = (int)(b > wb ? (b - wb < 4 ? b - wb : 4) : 0);
+              bad &= byte_span_mask(lo, hi);
+            }
+            found |= bad;
           }
         }
       }
@@ -3080,6 +3099,35 @@ __global__ __launch_bounds__(1024) void xd_scatter_kernel(const int32_t* seeds, 
   if (i < n_items) order[first[b] + rank] = i;
 }
 
+// Score of a seed: the sum of sim over its k symbol pairs, read a word of
+// codes at a time from each sequence (16 DNA or 4 byte codes per word; the
+// pieces of two stream words are joined with one funnel shift).
+template <int ALPHA>
+__device__ __forceinline__ int seed_score(const Params& P, const Src& S,
+                                          int64_t pa, int64_t pb, int k) {
+  constexpr int PER = ALPHA == 0 ? 16 : 4, BITS = ALPHA == 0 ? 2 : 8;
+  constexpr uint32_t MASK = ALPHA == 0 ? 3u : 31u;
+  auto piece = [&](int64_t pos) {  // PER codes from pos, lowest code lowest
+    const int64_t w = pos / PER;
+    const uint32_t sh = (uint32_t)(pos - w * PER) * BITS;
+    return funnel(load_word(S, w + 1), load_word(S, w), sh);
+  };
+  int sc = 0;
+  for (int u = 0; u < k; u += PER) {
+    const uint32_t wa = piece(pa + u), wb = piece(pb + u);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (u + j < k) {
+        const int ca = (int)((wa >> (BITS * j)) & MASK);
+        const int cb = (int)((wb >> (BITS * j)) & MASK);
+        if constexpr (ALPHA == 0) sc += ca == cb ? P.mat_s : P.mis_s;
+        else sc += P.table[ca * TABLE_DIM + cb];
+      }
+    }
+  }
+  return sc + 2 * P.gap * k;  // (the table holds sim - 2 gap)
+}
+
 // Seed level: score = left + seed score + right and positions (Sec. 4.1.1).
 // It is the last kernel of every batch, so it also finishes the batch's
 // bookkeeping: block 0 zeroes the queue and ordering counters for the next
@@ -3119,15 +3167,9 @@ __global__ __launch_bounds__(256) void xd_combine_kernel(Params P, void* out_v) 
         const int q = sd[0], t = sd[1], qp = sd[2], tp = sd[3], k = sd[4];
         const int64_t oq = P.offsets[q], ot = P.offsets[t];
         const Src S = make_src(P);
-        int seed = 0;
-        // (independent loads: unrolled so that a seed's symbols are in
-        // flight together)
-#pragma unroll 16
-        for (int u = 0; u < k; ++u) {
-          const int ca = sym_at(P, S, oq + qp + u), cb = sym_at(P, S, ot + tp + u);
-          if (P.alphabet == 0) seed += (ca == cb ? P.mat_s : P.mis_s) + 2 * P.gap;
-          else seed += P.table[ca * TABLE_DIM + cb] + 2 * P.gap;
-        }
+        const int seed =
+            P.alphabet == 0 ? seed_score<0>(P, S, oq + qp, ot + tp, k)
+                            : seed_score<1>(P, S, oq + qp, ot + tp, k);
         o.left = L.best; o.right = R.best; o.seed_score = seed;
         o.score = L.best + seed + R.best;
         o.q_begin = qp - L.x; o.t_begin = tp - L.y;

@@ -36,6 +36,9 @@ struct dim3 {
 struct uint2 {
   uint32_t x, y;
 };
+struct alignas(16) uint4 {
+  uint32_t x, y, z, w;
+};
 struct int4 {
   int x, y, z, w;
 };

@@ -263,3 +263,39 @@ def test_row_kernels_long_extensions(emu, variant, tier, X):
     g = emu.run(b, product_scoring(s), xdrop.options(variant=variant))
     assert not compare(g, oracle_run(b, s))
     assert emu.last_stats()[tier] == 12
+
+
+@pytest.mark.parametrize("asize", [20, 32])
+def test_symbol_check(emu, asize):
+    """The symbol check on the CPU build: out-of-alphabet codes (just above
+    the alphabet, up to 127, and 128..255) in the first, last or any byte of
+    sequences of 1..130 bytes that share words and 16-byte pieces with their
+    neighbours; a bad code in a neighbour never marks a sequence.  Statuses
+    and results equal the oracle's seed by seed."""
+    rng = np.random.default_rng([41, asize])
+    pairs, n_bad = [], 0
+    for i in range(300):
+        lq = int(rng.integers(1, 131))
+        q = rng.integers(0, asize, lq).astype(np.uint8)
+        t = q.copy()
+        kind = i % 6
+        if kind == 1:
+            q[0] = asize + int(rng.integers(0, 128 - asize))
+        elif kind == 2:
+            t[-1] = asize + int(rng.integers(0, 128 - asize))
+        elif kind == 3:
+            q[int(rng.integers(0, lq))] = int(rng.integers(128, 256))
+        elif kind == 4:
+            t[int(rng.integers(0, lq))] = 255
+        n_bad += kind in (1, 2, 3, 4)
+        k = int(rng.integers(0, min(lq, 6) + 1))
+        pos = int(rng.integers(0, lq - k + 1))
+        pairs.append((q, t, pos, pos, k))
+    b = make_batch(pairs, asize)
+    m = rng.integers(-4, 9, (asize, asize)).astype(np.int32)
+    m = np.minimum(m, m.T)
+    np.fill_diagonal(m, 5)
+    s = inputs.Scheme(asize, gap=-2, X=10, matrix=m)
+    g = emu.run(b, product_scoring(s))
+    assert not compare(g, oracle_run(b, s))
+    assert (g["status"] == xdrop.E_SYMBOL).sum() == n_bad
