@@ -45,6 +45,9 @@
 #ifndef XD_KB1
 #define XD_KB1 48  // antidiagonals per block of the one-cell loop
 #endif
+#ifndef XD_KB2
+#define XD_KB2 48  // antidiagonals per block of the two-cell loop
+#endif
 namespace xd {
 
 // ------------------------------------------------------------------ helpers
@@ -1091,9 +1094,11 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     return false;
   };
   // blocks of QB antidiagonals; the codes entering lane 0 during a block
-  // are read from the ring at its start (one word of DNA codes, four words
-  // of byte codes)
-  constexpr int QB = 16;
+  // are read from the ring at its start (QB / 16 words of DNA codes, QB / 4
+  // words of byte codes)
+  constexpr int QB = XD_KB2;
+  static_assert(QB % 16 == 0 && QB + 2 <= 64 && QB / 4 < Ring<1>::MIRROR,
+                "whole code words; the masks of a block fit in 64 lanes");
   int x[C], y[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) { x[j] = A[j]; y[j] = B[j]; }
@@ -1129,14 +1134,16 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     rem = d_end - d;
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + QB - 1);
-    uint32_t qw[ALPHA == 0 ? 1 : 4];
+    constexpr int NQ = ALPHA == 0 ? QB / 16 : QB / 4;
+    uint32_t qw[NQ];
     if constexpr (ALPHA == 0) {
-      qw[0] = Ring<0>::read(w.rb, e0);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) qw[i] = Ring<0>::read(w.rb, e0 + 16 * i);
     } else {
-      Ring<1>::read<4>(w.rb, e0, qw);
+      Ring<1>::read<NQ>(w.rb, e0, qw);
     }
 #pragma unroll
-    for (int i = 0; i < (ALPHA == 0 ? 1 : 4); ++i)
+    for (int i = 0; i < NQ; ++i)
       qw[i] = (uint32_t)in_vgpr((int)qw[i]);
     ml0 = xd_writelane_i32((int)(uint32_t)my0, 0, ml0);
     mh0 = xd_writelane_i32((int)(uint32_t)(my0 >> 32), 0, mh0);
@@ -1152,10 +1159,10 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
 #pragma unroll
       for (int k = 0; k < QB; k += 2) {
         const int in0 = ALPHA == 0
-            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k, 2)
+            ? (int)__builtin_amdgcn_ubfe(qw[k >> 4], 2 * (k & 15), 2)
             : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
         const int in1 = ALPHA == 0
-            ? (int)__builtin_amdgcn_ubfe(qw[0], 2 * k + 2, 2)
+            ? (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 4], 2 * ((k + 1) & 15), 2)
             : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
         if (body(edge_tag, x, y, mx0, mx1, my0, my1, in0, k)) {
           nk = k + 1; newest_in_y = true; return;
@@ -1200,7 +1207,8 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       const int hi = min(max(Ua, Ub) + 1, mrel);
       const bool live = Ua >= 0 || Ub >= 0;
       const int cnt = (kk >= 0 && kk < nk && live) ? max(hi - lo + 1, 0) : 0;
-      acc += (uint32_t)sum_lanes_0_31(cnt);
+      // (lanes 2 .. QB + 1 hold counts)
+      acc += (uint32_t)(QB + 2 <= 32 ? sum_lanes_0_31(cnt) : sum_lanes(cnt));
     }
     d += nk;
     if (newest_in_y) {
