@@ -971,9 +971,13 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   const int gap = P.gap, X = smin(P.X, 1 << 29);  // see fast_interior
   const int m = e.m, n = e.n;
   const int vmat = in_vgpr(P.mat_s), vmis = in_vgpr(P.mis_s);
-  // bare codes: cell j of lane l is x = base + 2l + j and takes a[x - 1]
-  // and b[d - x - 1]
-  int fa[C], fb[C];
+  // cell j of lane l is x = base + 2l + j and takes a[x - 1] and
+  // b[d - x - 1]: DNA keeps bare codes of both (the target codes move one
+  // cell up per antidiagonal); bytes keep the byte offset of the score
+  // table's row for a[x - 1] and read b[d - x - 1] from the ring per lane
+  // (cell 0 at an immediate offset per antidiagonal, cell 1 the code cell 0
+  // had one antidiagonal before)
+  int fa[C], fb[C] = {};
   auto load_fa = [&]() {
     const int sa = base + lane * C - 1;
     if constexpr (ALPHA == 0) {
@@ -985,24 +989,27 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       Ring<1>::read<1>(w.ra, sa, ta);
 #pragma unroll
       for (int j = 0; j < C; ++j)
-        fa[j] = (int)((ta[0] >> (8 * j)) & 31u) * TAB_LD;
+        fa[j] = (int)((ta[0] >> (8 * j)) & 31u) * (4 * TAB_LD);
     }
   };
   load_fa();
-  {
+  if constexpr (ALPHA == 0) {
     const int sb = d0 - base - lane * C - C;  // b index of cell C-1
-    if constexpr (ALPHA == 0) {
-      const uint32_t wb = Ring<0>::read(w.rb, sb);
+    const uint32_t wb = Ring<0>::read(w.rb, sb);
 #pragma unroll
-      for (int j = 0; j < C; ++j) fb[j] = (int)((wb >> (2 * (C - 1 - j))) & 3u);
-    } else {
-      uint32_t tb[1];
-      Ring<1>::read<1>(w.rb, sb, tb);
-#pragma unroll
-      for (int j = 0; j < C; ++j)
-        fb[j] = (int)((tb[0] >> (8 * (C - 1 - j))) & 31u);
-    }
+    for (int j = 0; j < C; ++j) fb[j] = (int)((wb >> (2 * (C - 1 - j))) & 3u);
   }
+  // bytes: the lane's ring position of cell 0's code on the block's first
+  // antidiagonal; the two cells' scores of the next antidiagonal, cell 0's
+  // code on the current one and its codes of the two after the next are
+  // read ahead of their use (as in the one-cell loop)
+  const uint8_t* cp = reinterpret_cast<const uint8_t*>(w.rb);
+  int sc0 = 0, sc1 = 0;
+  uint32_t ccur = 0, cd1 = 0, cd2 = 0;
+  auto score = [&](int f, uint32_t c) {
+    return *reinterpret_cast<const int*>(
+        reinterpret_cast<const char*>(tab) + f + (c << 2));
+  };
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
   uint32_t acc = 0;         // live-span cells of the antidiagonals done
@@ -1033,8 +1040,18 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
                                                   false);
       int sim;
       if constexpr (ALPHA == 0) sim = fa[j] == fb[j] ? vmat : vmis;
-      else sim = tab[fa[j] + fb[j]];
+      else sim = j == 0 ? sc0 : sc1;
       v[j] = max(max(up, prev[j]), dg + sim);
+    }
+    if constexpr (ALPHA == 1) {
+      // next antidiagonal: cell 1 takes cell 0's current code
+      sc1 = score(fa[1], ccur);
+      ccur = cd1;
+      sc0 = score(fa[0], cd1);
+      cd1 = cd2;
+      int c3 = cp[k + 3];
+      opaque_v(c3);  // (the load's zero extension stays with it)
+      cd2 = (uint32_t)c3;
     }
     uint64_t f[C];
 #pragma unroll
@@ -1076,11 +1093,13 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     ml1 = xd_writelane_i32((int)(uint32_t)f[1], k + 2, ml1);
     mh1 = xd_writelane_i32((int)(uint32_t)(f[1] >> 32), k + 2, mh1);
     tv -= gap;
-    // the target codes move one cell up; lane 0 takes `in`
-    const int top = fb[C - 1];
+    if constexpr (ALPHA == 0) {
+      // the target codes move one cell up; lane 0 takes `in`
+      const int top = fb[C - 1];
 #pragma unroll
-    for (int j = C - 1; j > 0; --j) fb[j] = fb[j - 1];
-    fb[0] = __builtin_amdgcn_update_dpp(in, top, 0x138, 0xf, 0xf, false);
+      for (int j = C - 1; j > 0; --j) fb[j] = fb[j - 1];
+      fb[0] = __builtin_amdgcn_update_dpp(in, top, 0x138, 0xf, 0xf, false);
+    }
     if (k & 1) {
       const uint64_t o = mp0 | mp1 | f[0] | f[1];
       if (o == 0) return true;
@@ -1097,8 +1116,9 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   // are read from the ring at its start (QB / 16 words of DNA codes, QB / 4
   // words of byte codes)
   constexpr int QB = XD_KB2;
-  static_assert(QB % 16 == 0 && QB + 2 <= 64 && QB / 4 < Ring<1>::MIRROR,
-                "whole code words; the masks of a block fit in 64 lanes");
+  static_assert(QB % 16 == 0 && QB + 2 <= 64 && QB + 3 <= 4 * Ring<1>::MIRROR,
+                "whole DNA code words; the masks of a block fit in 64 lanes; "
+                "byte reads stay within the ring's mirror words");
   int x[C], y[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) { x[j] = A[j]; y[j] = B[j]; }
@@ -1116,10 +1136,11 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
         for (int j = 0; j < C; ++j) {
           const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x[j]);
           const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y[j]);
-          // target codes move with their cells; stray codes at the top
-          // lanes are not used before they have moved out (see
+          // DNA: target codes move with their cells; stray codes at the
+          // top lanes are not used before they have moved out (see
           // fast_interior)
-          fb[j] = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb[j]);
+          if constexpr (ALPHA == 0)
+            fb[j] = __builtin_amdgcn_ds_bpermute((src & 63) << 2, fb[j]);
           x[j] = in ? pn : NEG;
           y[j] = in ? po : NEG;
         }
@@ -1134,17 +1155,23 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     rem = d_end - d;
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + QB - 1);
-    constexpr int NQ = ALPHA == 0 ? QB / 16 : QB / 4;
-    uint32_t qw[NQ];
+    constexpr int NQ = ALPHA == 0 ? QB / 16 : 1;
+    uint32_t qw[NQ] = {};
     if constexpr (ALPHA == 0) {
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) qw[i] = Ring<0>::read(w.rb, e0 + 16 * i);
+      for (int i = 0; i < NQ; ++i)
+        qw[i] = (uint32_t)in_vgpr((int)Ring<0>::read(w.rb, e0 + 16 * i));
     } else {
-      Ring<1>::read<NQ>(w.rb, e0, qw);
+      // (reads up to QB + 2 bytes past a ring position, which the mirror
+      // words cover)
+      const uint8_t* rbb = reinterpret_cast<const uint8_t*>(w.rb);
+      cp = rbb + ((e0 - 2 * lane - 1) & (Ring<1>::RS - 1));
+      ccur = cp[0];
+      sc0 = score(fa[0], ccur);
+      sc1 = score(fa[1], rbb[(e0 - 2 * lane - 2) & (Ring<1>::RS - 1)]);
+      cd1 = cp[1];
+      cd2 = cp[2];
     }
-#pragma unroll
-    for (int i = 0; i < NQ; ++i)
-      qw[i] = (uint32_t)in_vgpr((int)qw[i]);
     ml0 = xd_writelane_i32((int)(uint32_t)my0, 0, ml0);
     mh0 = xd_writelane_i32((int)(uint32_t)(my0 >> 32), 0, mh0);
     ml1 = xd_writelane_i32((int)(uint32_t)my1, 0, ml1);
@@ -1159,11 +1186,10 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
 #pragma unroll
       for (int k = 0; k < QB; k += 2) {
         const int in0 = ALPHA == 0
-            ? (int)__builtin_amdgcn_ubfe(qw[k >> 4], 2 * (k & 15), 2)
-            : (int)__builtin_amdgcn_ubfe(qw[k >> 2], 8 * (k & 3), 5);
+            ? (int)__builtin_amdgcn_ubfe(qw[k >> 4], 2 * (k & 15), 2) : 0;
         const int in1 = ALPHA == 0
             ? (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 4], 2 * ((k + 1) & 15), 2)
-            : (int)__builtin_amdgcn_ubfe(qw[(k + 1) >> 2], 8 * ((k + 1) & 3), 5);
+            : 0;
         if (body(edge_tag, x, y, mx0, mx1, my0, my1, in0, k)) {
           nk = k + 1; newest_in_y = true; return;
         }
