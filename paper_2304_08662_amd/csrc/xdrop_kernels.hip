@@ -633,17 +633,17 @@ __device__ __forceinline__ int in_vgpr(int v) {
 // antidiagonals that stay clear of both edges skip them and the per-lane
 // edge masks.  The live-span count
 // sum(hi_d - lo_d + 1) is formed once per block on the vector unit from the
-// masks, which the block keeps in lanes of two registers.  The top G = 4
-// lanes stay -infinity at the start of every group of G antidiagonals (the
+// masks, which the block keeps in lanes of two registers.  The top G lanes
+// (8 for DNA, 4 for byte codes) stay -infinity at the start of every group
+// of G antidiagonals (the
 // band grows by at most one lane per antidiagonal, so the top lane is still
 // -infinity G - 1 antidiagonals later): the neighbour exchange is then a
 // wave rotation that brings -infinity to lane 0, and the band is tested
 // against the top only every G-th antidiagonal.  When the band reaches lane
 // 64 - G the window slides up in place by the dead lanes below the band.
 // DNA scores come from per-block match words (bit 2k of lane l: the codes
-// of cell base + l agree on antidiagonal d + k); byte codes move one cell up
-// per antidiagonal, lane 0 taking the next queued code, and index the score
-// table.  The loop computes antidiagonals up to m + n - 1 and hands over to
+// of cell base + l agree on antidiagonal d + k); byte codes are read per
+// lane from the ring and index the score table.  The loop computes antidiagonals up to m + n - 1 and hands over to
 // the generic step (state as that step expects) at the last one, after two
 // dead antidiagonals, or when the band fills the window; R_ESC when the
 // window can neither slide nor stay.
@@ -709,8 +709,12 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   static_assert(KB % 16 == 0 && KB + 2 <= 64,
                 "whole DNA match words; the masks of a block fit in 64 lanes");
   // top lanes kept -infinity between the tests against the top, which run
-  // with the dead test, every fourth antidiagonal
-  constexpr int G = 4;
+  // with the dead test every G-th antidiagonal.  Fewer tests cost a smaller
+  // window: DNA bands are narrow and its chains long (8: dna-tail 6.05 ->
+  // 5.70 ms, dna-1k 0.158 -> 0.150), protein bands wider (4: 2 and 8 were
+  // 1.5% and 3.4% slower on protein-500k)
+  constexpr int G = ALPHA == 0 ? 8 : 4;
+  static_assert(KB % G == 0, "tests fall on the same steps in every block");
   uint32_t mw[KB / 16] = {};  // DNA: match words of the block (16 steps each)
   // finite-lane masks of the block's antidiagonals for the live-span count,
   // kept in lanes of two registers (low and high words): lanes 0 and 1 hold
@@ -728,10 +732,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // Antidiagonal d + k from prev (d+k-1) and pp (d+k-2), with their
   // finite-lane masks mp and mpp; pp and mpp receive d + k (the two
   // antidiagonals and their masks swap roles every step).  True (k = G - 1
-  // mod G) when the band reached lane 64 - G, (k = 3 mod 4) after two dead
+  // mod G) when the band reached lane 64 - G or after two dead
   // antidiagonals, or (edge blocks) at the last antidiagonal of the range;
   // the reason is read from the masks and d after the block.  (Two dead
-  // antidiagonals may be followed by up to three more, dead as well, that
+  // antidiagonals may be followed by up to G - 1 more, dead as well, that
   // add no live-span cell.)  d itself moves once per block.
   auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
                   uint64_t& mpp, int k) -> bool {
@@ -798,7 +802,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     tv -= gap;
     if ((k & (G - 1)) == G - 1) {
       const uint64_t o = mp | fm;
-      if ((k & 3) == 3 && o == 0) return true;
+      if (o == 0) return true;
       // one of the top G lanes finite; tested on the high word, since a
       // 64-bit compare would run on the vector unit
       uint32_t hw = (uint32_t)(o >> 32);
