@@ -48,6 +48,9 @@
 #ifndef XD_KB2
 #define XD_KB2 48  // antidiagonals per block of the two-cell loop
 #endif
+#ifndef XD_G2
+#define XD_G2 2  // guard lanes of the two-cell loop
+#endif
 namespace xd {
 
 // ------------------------------------------------------------------ helpers
@@ -960,6 +963,10 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
                                                    const Params& P,
                                                    const Src& S) {
   static_assert(C == 2, "two cells per lane");
+  // top lanes kept -infinity between the tests against the top, which run
+  // with the dead test every G2-th antidiagonal
+  constexpr int G2 = XD_G2;
+  static_assert(XD_KB2 % G2 == 0, "tests fall on the same steps in every block");
   int base = e.base;
   if (P.band_cap > 0) return R_CONT;
   const int d_last = e.m + e.n - 1;
@@ -1104,12 +1111,12 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       for (int j = C - 1; j > 0; --j) fb[j] = fb[j - 1];
       fb[0] = __builtin_amdgcn_update_dpp(in, top, 0x138, 0xf, 0xf, false);
     }
-    if (k & 1) {
+    if ((k & (G2 - 1)) == G2 - 1) {
       const uint64_t o = mp0 | mp1 | f[0] | f[1];
       if (o == 0) return true;
-      uint32_t hw = (uint32_t)(o >> 32);  // lanes 62, 63 (see fast_interior)
+      uint32_t hw = (uint32_t)(o >> 32);  // the top G2 lanes (see fast_interior)
       opaque_s(hw);
-      if (hw >= (1u << 30)) return true;
+      if (hw >= (1u << (32 - G2))) return true;
     }
     if constexpr (EDGE) {
       if (k >= rem) return true;  // d + k is d_end
@@ -1129,11 +1136,11 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   while (d <= d_end) {
     {
       const uint64_t o = mx0 | mx1 | my0 | my1;
-      if ((uint32_t)(o >> 32) >= (1u << 30)) {
+      if ((uint32_t)(o >> 32) >= (1u << (32 - G2))) {
         // the band reached lane 62: slide the window up by the whole lanes
         // below the lowest finite cell of d-1 and d-2
         const int sl = __builtin_ctzll(o);
-        if (sl < 2) break;
+        if (sl < G2) break;
         const int src = lane + sl;
         const bool in = src < 64;
 #pragma unroll
