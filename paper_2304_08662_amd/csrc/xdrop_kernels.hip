@@ -646,9 +646,10 @@ __device__ __forceinline__ int in_vgpr(int v) {
 // 64 - G the window slides up in place by the dead lanes below the band.
 // DNA scores come from per-block match words (bit 2k of lane l: the codes
 // of cell base + l agree on antidiagonal d + k); byte codes are read per
-// lane from the ring and index the score table.  The loop computes antidiagonals up to m + n - 1 and hands over to
-// the generic step (state as that step expects) at the last one, after two
-// dead antidiagonals, or when the band fills the window; R_ESC when the
+// lane from the ring and index the score table.  The loop computes
+// antidiagonals up to m + n and returns R_DONE after the last one or after
+// two dead antidiagonals; it hands over to the generic step (state as that
+// step expects) when the band fills the window, and returns R_ESC when the
 // window can neither slide nor stay.
 template <int ALPHA>
 __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
@@ -658,7 +659,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
                                              const Src& S) {
   int base = e.base;
   if (P.band_cap > 0) return R_CONT;
-  const int d_last = e.m + e.n - 1;  // antidiagonals this loop may compute
+  const int d_last = e.m + e.n;  // antidiagonals this loop may compute
   if (e.d > d_last) return R_CONT;
   uint64_t m1 = e.L1 > e.U1 ? 0
                 : (1ull << (e.L1 - base)) | (1ull << (e.U1 - base));
@@ -931,15 +932,20 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     e.bx = bxa;
     e.by = bd - bxa;
   }
-  e.L1 = m1 ? base + __builtin_ctzll(m1) : DEAD_L;
-  e.U1 = m1 ? base + 63 - __builtin_clzll(m1) : DEAD_U;
-  e.L2 = m2 ? base + __builtin_ctzll(m2) : DEAD_L;
-  e.U2 = m2 ? base + 63 - __builtin_clzll(m2) : DEAD_U;
-  int r = R_CONT;
-  const int mv = window_move<ALPHA, 1>(e, A, B, sy, w, S, e.L1, e.L2, e.U1,
-                                       e.U2);
-  if (mv == MV_ESC) r = R_ESC;
-  else if (mv == MV_NONE) reload_syms<ALPHA, 1>(e, sy, w, S);
+  // finished: two dead antidiagonals (every later cell is -infinity) or the
+  // last antidiagonal of the matrix computed
+  int r = R_DONE;
+  if ((m1 | m2) != 0 && d <= e.m + e.n) {
+    e.L1 = m1 ? base + __builtin_ctzll(m1) : DEAD_L;
+    e.U1 = m1 ? base + 63 - __builtin_clzll(m1) : DEAD_U;
+    e.L2 = m2 ? base + __builtin_ctzll(m2) : DEAD_L;
+    e.U2 = m2 ? base + 63 - __builtin_clzll(m2) : DEAD_U;
+    r = R_CONT;
+    const int mv = window_move<ALPHA, 1>(e, A, B, sy, w, S, e.L1, e.L2, e.U1,
+                                         e.U2);
+    if (mv == MV_ESC) r = R_ESC;
+    else if (mv == MV_NONE) reload_syms<ALPHA, 1>(e, sy, w, S);
+  }
   make_uniform(e);
   return r;
 }
@@ -1273,6 +1279,7 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     e.bx = bxa;
     e.by = bd - bxa;
   }
+
   auto lo_of = [&](uint64_t m0, uint64_t m1) {
     return smin(m0 ? 2 * __builtin_ctzll(m0) : DEAD_L,
                 m1 ? 2 * __builtin_ctzll(m1) + 1 : DEAD_L);
