@@ -741,9 +741,10 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // the reason is read from the masks and d after the block.  (Two dead
   // antidiagonals may be followed by up to G - 1 more, dead as well, that
   // add no live-span cell.)  d itself moves once per block.
-  auto body = [&](auto edge_tag, int& prev, int& pp, const uint64_t& mp,
-                  uint64_t& mpp, int k) -> bool {
+  auto body = [&](auto edge_tag, auto g_tag, int& prev, int& pp,
+                  const uint64_t& mp, uint64_t& mpp, int k) -> bool {
     constexpr bool EDGE = decltype(edge_tag)::value;
+    constexpr int GG = decltype(g_tag)::value;  // G, or 1 (narrow top room)
     const int thr = tv - X;
     int sim;
     if constexpr (ALPHA == 0) {
@@ -804,14 +805,14 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     ml = xd_writelane_i32((int)(uint32_t)fm, k + 2, ml);
     mh = xd_writelane_i32((int)(uint32_t)(fm >> 32), k + 2, mh);
     tv -= gap;
-    if ((k & (G - 1)) == G - 1) {
+    if ((k & (GG - 1)) == GG - 1) {
       const uint64_t o = mp | fm;
       if (o == 0) return true;
-      // one of the top G lanes finite; tested on the high word, since a
+      // one of the top GG lanes finite; tested on the high word, since a
       // 64-bit compare would run on the vector unit
       uint32_t hw = (uint32_t)(o >> 32);
       opaque_s(hw);
-      if (hw >= (1u << (32 - G))) return true;
+      if (hw >= (1u << (32 - GG))) return true;
     }
     if constexpr (EDGE) {
       if (k >= rem) return true;  // d + k is d_end
@@ -822,24 +823,36 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   // x (mask m1) holds d-1 and y (mask m2) holds d-2 at the start of a block
   int x = A[0], y = B[0];
   while (d <= d_end) {
+    // byte codes: a band with fewer than G free lanes above it after the
+    // slide runs a block with one guard lane, tested every antidiagonal (a
+    // band that fills the window goes to the generic step, which widens the
+    // tile).  Protein bands hover near the window's width: this replaced a
+    // hand-over to the generic step and back for 14% of protein-500k's
+    // extensions, 8.7 times each (10.22 -> 9.67 ms).  DNA bands are narrow;
+    // there the extra block copy cost 5-9% (register allocation), so DNA
+    // hands over as before.
+    bool tight = false;
     if (cz < G) {
       // the band reached lane 64 - G: slide the window up by the lanes
       // below the lowest finite cell of d-1 and d-2 (they are -infinity on
       // both)
       const int sl = __builtin_ctzll(m1 | m2);
-      if (cz + sl < G) break;
-      const int src = lane + sl;
-      const bool in = src < 64;
-      const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
-      const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y);
-      x = in ? pn : NEG;
-      y = in ? po : NEG;
-      m1 >>= sl;
-      m2 >>= sl;
-      cz += sl;
-      base += sl;
-      cover_a<ALPHA>(e, w, S, base + 62);
-      load_fa();
+      if (cz + sl < (ALPHA == 1 ? 1 : G)) break;
+      if (ALPHA == 0 || sl > 0) {  // (DNA: sl > 0 here)
+        const int src = lane + sl;
+        const bool in = src < 64;
+        const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
+        const int po = __builtin_amdgcn_ds_bpermute((src & 63) << 2, y);
+        x = in ? pn : NEG;
+        y = in ? po : NEG;
+        m1 >>= sl;
+        m2 >>= sl;
+        cz += sl;
+        base += sl;
+        cover_a<ALPHA>(e, w, S, base + 62);
+        load_fa();
+      }
+      if constexpr (ALPHA == 1) tight = cz < G;
     }
     pm = d - n - base;
     mrel = m - base;
@@ -869,19 +882,21 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     mh = xd_writelane_i32((int)(uint32_t)(m1 >> 32), 1, mh);
     int nk = KB;  // antidiagonals computed by the block
     bool newest_in_y = false;
-    auto run_block = [&](auto edge_tag) {
+    auto run_block = [&](auto edge_tag, auto g_tag) {
 #pragma unroll
       for (int k = 0; k < KB; k += 2) {
-        if (body(edge_tag, x, y, m1, m2, k)) {
+        if (body(edge_tag, g_tag, x, y, m1, m2, k)) {
           nk = k + 1; newest_in_y = true; return;
         }
-        if (body(edge_tag, y, x, m2, m1, k + 1)) { nk = k + 2; return; }
+        if (body(edge_tag, g_tag, y, x, m2, m1, k + 1)) { nk = k + 2; return; }
       }
     };
-    if (pm + KB - 1 <= 0 && mrel >= 63 && rem >= KB - 1)
-      run_block(std::false_type{});
+    if (ALPHA == 1 && tight)  // (its own copy with the edge masks)
+      run_block(std::true_type{}, std::integral_constant<int, 1>{});
+    else if (pm + KB - 1 <= 0 && mrel >= 63 && rem >= KB - 1)
+      run_block(std::false_type{}, std::integral_constant<int, G>{});
     else
-      run_block(std::true_type{});
+      run_block(std::true_type{}, std::integral_constant<int, G>{});
     {
       // live-span cells of the block's antidiagonals, one per lane k + 2,
       // from the masks of the two antidiagonals before each (lanes k + 1 and
