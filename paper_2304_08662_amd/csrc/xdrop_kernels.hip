@@ -51,6 +51,12 @@
 #ifndef XD_G2
 #define XD_G2 2  // guard lanes of the two-cell loop
 #endif
+#ifndef XD_PRE
+#define XD_PRE 16  // byte codes: slide early with fewer free lanes than G + this
+#endif
+#ifndef XD_MINSL
+#define XD_MINSL 4  // ... by at least this many lanes
+#endif
 namespace xd {
 
 // ------------------------------------------------------------------ helpers
@@ -831,14 +837,18 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     // extensions, 8.7 times each (10.22 -> 9.67 ms).  DNA bands are narrow;
     // there the extra block copy cost 5-9% (register allocation), so DNA
     // hands over as before.
+    // Byte codes also slide early: a band with fewer than G + XD_PRE free
+    // lanes above it would likely reach the top within the block, which then
+    // ends early (0.5% on protein-500k; DNA's narrow bands lost 1-2%).
+    constexpr int EARLY = ALPHA == 1 ? XD_PRE : 0;
     bool tight = false;
-    if (cz < G) {
+    if (cz < G + EARLY) {
       // the band reached lane 64 - G: slide the window up by the lanes
       // below the lowest finite cell of d-1 and d-2 (they are -infinity on
       // both)
       const int sl = __builtin_ctzll(m1 | m2);
-      if (cz + sl < (ALPHA == 1 ? 1 : G)) break;
-      if (ALPHA == 0 || sl > 0) {  // (DNA: sl > 0 here)
+      if (cz < G && cz + sl < (ALPHA == 1 ? 1 : G)) break;
+      if (cz < G ? (ALPHA == 0 || sl > 0) : sl >= XD_MINSL) {
         const int src = lane + sl;
         const bool in = src < 64;
         const int pn = __builtin_amdgcn_ds_bpermute((src & 63) << 2, x);
