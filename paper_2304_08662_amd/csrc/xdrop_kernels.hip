@@ -43,7 +43,10 @@
 #include "xdrop_internal.h"
 
 #ifndef XD_KB1
-#define XD_KB1 48  // antidiagonals per block of the one-cell loop
+#define XD_KB1 48  // antidiagonals per block of the one-cell loop (DNA)
+#endif
+#ifndef XD_KB1B
+#define XD_KB1B 60  // ... for byte codes (48: 0.4% slower on protein-500k)
 #endif
 #ifndef XD_KB2
 #define XD_KB2 48  // antidiagonals per block of the two-cell loop
@@ -244,9 +247,10 @@ template <int RS_, int NT>
 struct RingT<1, RS_, NT> {  // one byte per code
   static constexpr int RS = RS_;
   static constexpr int RW = RS / 4;
-  // reads of up to 8 words, and the one-cell loop's per-lane code reads up
-  // to XD_KB1 + 2 bytes past a position
-  static constexpr int MIRROR = (XD_KB1 + 6) / 4 > 9 ? (XD_KB1 + 6) / 4 : 9;
+  // reads of up to 8 words, and the per-lane code reads of the one- and
+  // two-cell loops up to a block's length + 2 bytes past a position
+  static constexpr int KMAX = XD_KB1B > XD_KB2 ? XD_KB1B : XD_KB2;
+  static constexpr int MIRROR = (KMAX + 6) / 4 > 9 ? (KMAX + 6) / 4 : 9;
   static constexpr int WORDS = RW + MIRROR;
   static constexpr int CH = 8 * NT;        // elements per fill (8 per thread)
 
@@ -639,7 +643,7 @@ __device__ __forceinline__ int in_vgpr(int v) {
 //   lo_d = max(ctz(M1 | M2 << 1), d - n - base),
 //   hi_d = min(64 - clz(M1 | M2), m - base),
 // where the clamps matter only near the matrix edges; blocks of XD_KB1
-// antidiagonals that stay clear of both edges skip them and the per-lane
+// (DNA) or XD_KB1B (byte codes) antidiagonals that stay clear of both edges skip them and the per-lane
 // edge masks.  The live-span count
 // sum(hi_d - lo_d + 1) is formed once per block on the vector unit from the
 // masks, which the block keeps in lanes of two registers.  The top G lanes
@@ -713,10 +717,12 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   uint64_t in_m = 0;        // edge blocks: the lanes with x <= m
   int rem = 0;              // edge blocks: d_end - d
   // antidiagonals per block (the block's fixed work, some 60 vector
-  // instructions, spreads over its steps; 48 measured 3-5% faster than 32):
-  // DNA reads KB / 16 match words, bytes take their codes from the ring
-  constexpr int KB = XD_KB1;
-  static_assert(KB % 16 == 0 && KB + 2 <= 64,
+  // instructions, spreads over its steps; 48 measured 3-5% faster than 32,
+  // and 60 another 0.4% for byte codes, whose blocks need no whole match
+  // words): DNA reads KB / 16 match words, bytes take their codes from the
+  // ring
+  constexpr int KB = ALPHA == 1 ? XD_KB1B : XD_KB1;
+  static_assert((ALPHA == 1 || KB % 16 == 0) && KB + 2 <= 64,
                 "whole DNA match words; the masks of a block fit in 64 lanes");
   // top lanes kept -infinity between the tests against the top, which run
   // with the dead test every G-th antidiagonal.  Fewer tests cost a smaller
