@@ -49,13 +49,16 @@
 #define XD_KB1B 60  // ... for byte codes (48: 0.4% slower on protein-500k)
 #endif
 #ifndef XD_KB2
-#define XD_KB2 48  // antidiagonals per block of the two-cell loop
+#define XD_KB2 48  // antidiagonals per block of the two-cell loop (DNA)
+#endif
+#ifndef XD_KB2B
+#define XD_KB2B 56  // ... for byte codes (48 and 60: 0.15% slower on protein-500k)
 #endif
 #ifndef XD_G2
 #define XD_G2 2  // guard lanes of the two-cell loop
 #endif
 #ifndef XD_PRE
-#define XD_PRE 16  // byte codes: slide early with fewer free lanes than G + this
+#define XD_PRE 24  // byte codes: slide early with fewer free lanes than G + this
 #endif
 #ifndef XD_MINSL
 #define XD_MINSL 4  // ... by at least this many lanes
@@ -249,7 +252,7 @@ struct RingT<1, RS_, NT> {  // one byte per code
   static constexpr int RW = RS / 4;
   // reads of up to 8 words, and the per-lane code reads of the one- and
   // two-cell loops up to a block's length + 2 bytes past a position
-  static constexpr int KMAX = XD_KB1B > XD_KB2 ? XD_KB1B : XD_KB2;
+  static constexpr int KMAX = XD_KB1B > XD_KB2B ? XD_KB1B : XD_KB2B;
   static constexpr int MIRROR = (KMAX + 6) / 4 > 9 ? (KMAX + 6) / 4 : 9;
   static constexpr int WORDS = RW + MIRROR;
   static constexpr int CH = 8 * NT;        // elements per fill (8 per thread)
@@ -856,7 +859,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
     // hands over as before.
     // Byte codes also slide early: a band with fewer than G + XD_PRE free
     // lanes above it would likely reach the top within the block, which then
-    // ends early (0.5% on protein-500k; DNA's narrow bands lost 1-2%).
+    // ends early (protein-500k: 0.5% with blocks of 48 and a margin of 16,
+    // another 0.6% with blocks of 60 and a margin of 24, where margins of
+    // 24 to 40 measure the same; DNA's narrow bands lost 1-2%).
     constexpr int EARLY = ALPHA == 1 ? XD_PRE : 0;
     bool tight = false;
     if (cz < G + EARLY) {
@@ -1014,7 +1019,8 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   // top lanes kept -infinity between the tests against the top, which run
   // with the dead test every G2-th antidiagonal
   constexpr int G2 = XD_G2;
-  static_assert(XD_KB2 % G2 == 0, "tests fall on the same steps in every block");
+  static_assert(XD_KB2 % G2 == 0 && XD_KB2B % G2 == 0,
+                "tests fall on the same steps in every block");
   int base = e.base;
   if (P.band_cap > 0) return R_CONT;
   const int d_last = e.m + e.n - 1;
@@ -1174,8 +1180,9 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   // blocks of QB antidiagonals; the codes entering lane 0 during a block
   // are read from the ring at its start (QB / 16 words of DNA codes, QB / 4
   // words of byte codes)
-  constexpr int QB = XD_KB2;
-  static_assert(QB % 16 == 0 && QB + 2 <= 64 && QB + 3 <= 4 * Ring<1>::MIRROR,
+  constexpr int QB = ALPHA == 1 ? XD_KB2B : XD_KB2;
+  static_assert((ALPHA == 1 || QB % 16 == 0) && QB + 2 <= 64 &&
+                    QB + 3 <= 4 * Ring<1>::MIRROR,
                 "whole DNA code words; the masks of a block fit in 64 lanes; "
                 "byte reads stay within the ring's mirror words");
   int x[C], y[C];
