@@ -711,7 +711,9 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
   load_fa();
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
-  uint32_t acc = 0;         // sum over d of (65 - live-span cells)
+  // per lane: the sum over the blocks of its antidiagonal's 65 - live-span
+  // cells (lanes 2 .. KB + 1); summed over the wave once, after the loop
+  int vacc = 0;
   // last new best: its antidiagonal, its x, and its lane (folded into x
   // once per block: base moves only between blocks); T itself follows from
   // tv, which is T in the frame of the next antidiagonal
@@ -951,7 +953,7 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       const int cnt = (kk >= 0 && kk < nk)
                           ? (live ? 65 - max(hi - lo + 1, 0) : 65) : 0;
       // (lanes 2 .. KB + 1 hold counts)
-      acc += (uint32_t)(KB + 2 <= 32 ? sum_lanes_0_31(cnt) : sum_lanes(cnt));
+      vacc += cnt;
     }
     if (bd >= d) bxa = base + bln;  // a new best in this block
     d += nk;
@@ -973,6 +975,8 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
 
   e.base = base;
   e.d = d;
+  const uint32_t acc =
+      (uint32_t)(KB + 2 <= 32 ? sum_lanes_0_31(vacc) : sum_lanes(vacc));
   e.W += (int64_t)65 * (d - d0) - (int64_t)acc;
   e.T = tv + gap * d;
   if (bd >= 0) {
@@ -1077,7 +1081,8 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   };
   int d = d0;
   int tv = e.T - gap * d0;  // best score in the frame of antidiagonal d
-  uint32_t acc = 0;         // live-span cells of the antidiagonals done
+  int vacc = 0;  // per lane: live-span cells of its antidiagonals (see
+                 // fast_interior), summed over the wave after the loop
   int tbest = 0, bd = -1, bxa = 0;
   int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
   int rem = 0;              // edge blocks: d_end - d
@@ -1300,7 +1305,7 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       const bool live = Ua >= 0 || Ub >= 0;
       const int cnt = (kk >= 0 && kk < nk && live) ? max(hi - lo + 1, 0) : 0;
       // (lanes 2 .. QB + 1 hold counts)
-      acc += (uint32_t)(QB + 2 <= 32 ? sum_lanes_0_31(cnt) : sum_lanes(cnt));
+      vacc += cnt;
     }
     d += nk;
     if (newest_in_y) {
@@ -1322,7 +1327,8 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   }
   e.base = base;
   e.d = d;
-  e.W += (int64_t)acc;
+  e.W += (int64_t)(uint32_t)(QB + 2 <= 32 ? sum_lanes_0_31(vacc)
+                                          : sum_lanes(vacc));
   if (bd >= 0) {
     e.T = tbest + gap * bd;
     e.bx = bxa;
