@@ -1086,6 +1086,7 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
   int tbest = 0, bd = -1, bxa = 0;
   int pm = 0, mrel = 0;     // edge blocks: d - n - base, m - base
   int rem = 0;              // edge blocks: d_end - d
+  uint64_t in_m0 = 0, in_m1 = 0;  // edge blocks: lanes whose cell j has x <= m
   // masks of the block's antidiagonals in lanes (lane k + 2: the block's
   // k-th; lanes 0 and 1: the two before it), per register j and word
   int ml0 = 0, mh0 = 0, ml1 = 0, mh1 = 0;
@@ -1127,9 +1128,14 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       f[j] = ballot(v[j] >= thr);
-      if constexpr (EDGE)  // y > n below pm, x > m above mrel
-        f[j] &= ballot((uint32_t)(lane * C + j - (pm + k)) <=
-                       (uint32_t)(mrel - (pm + k)));
+      if constexpr (EDGE) {
+        // y > n below pm + k (pm + k - j formed on the scalar unit: the
+        // compiler would otherwise form lane * C - k on the vector unit),
+        // x > m above mrel (block masks)
+        uint32_t pk = (uint32_t)(pm + k - j);
+        opaque_s(pk);
+        f[j] &= ballot(lane * C >= (int)pk) & (j ? in_m1 : in_m0);
+      }
     }
     int vn[C];
 #pragma unroll
@@ -1224,6 +1230,8 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
     pm = d - n - base;
     mrel = m - base;
     rem = d_end - d;
+    in_m0 = ballot(lane * C <= mrel);
+    in_m1 = ballot(lane * C + 1 <= mrel);
     const int e0 = d - base;
     cover_b<ALPHA>(e, w, S, e0 + QB - 1);
     constexpr int NQ = ALPHA == 0 ? QB / 16 : 1;
