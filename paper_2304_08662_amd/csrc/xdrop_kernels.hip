@@ -94,6 +94,25 @@ __device__ __forceinline__ void pin_v(int& v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ int wave_shr1(int v, int fill) {
   return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);
 }
+// Lane l receives lane l-1's value; lane 0 receives 0 (bound control: no
+// register holding the fill value to set first).
+__device__ __forceinline__ int wave_shr1_z(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
+}
+// The lowest / highest set bit of each lane's word, 0xffffffff for a zero
+// word (v_ffbl_b32, v_ffbh_u32).  Written out: the compiler's bit scans with
+// a fallback for zero add a compare and a select to each, eight vector
+// instructions per block of the sweeps.
+__device__ __forceinline__ uint32_t ffbl32(uint32_t x) {
+  uint32_t r;
+  asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+__device__ __forceinline__ uint32_t ffbh32(uint32_t x) {
+  uint32_t r;
+  asm("v_ffbh_u32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
 // Lane l receives lane l+1's value; lane 63 receives `fill`.
 __device__ __forceinline__ int wave_shl1(int v, int fill) {
   return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
@@ -941,14 +960,12 @@ __device__ __forceinline__ int fast_interior(Ext& e, int (&A)[1], int (&B)[1],
       // lo = ctz(M1 | M2 << 1), hi = 64 - clz(M1 | M2) (M2 never holds lane
       // 63, so neither search comes up empty unless both masks are zero: an
       // antidiagonal after two dead ones, with no live-span cell)
-      const uint32_t al = (uint32_t)wave_shr1(ml, 0), ah = (uint32_t)wave_shr1(mh, 0);
-      const uint32_t bl = (uint32_t)wave_shr1((int)al, 0), bh = (uint32_t)wave_shr1((int)ah, 0);
+      const uint32_t al = (uint32_t)wave_shr1_z(ml), ah = (uint32_t)wave_shr1_z(mh);
+      const uint32_t bl = (uint32_t)wave_shr1_z((int)al), bh = (uint32_t)wave_shr1_z((int)ah);
       const uint32_t cl = al | (bl << 1);
       const uint32_t ch = ah | __builtin_amdgcn_alignbit(bh, bl, 31);
-      const uint32_t ctz = min((uint32_t)__builtin_ctzg(cl, -1),
-                               (uint32_t)__builtin_ctzg(ch, -1) | 32u);
-      const uint32_t clz = min((uint32_t)__builtin_clzg(ah | bh, -1),
-                               (uint32_t)__builtin_clzg(al | bl, -1) | 32u);
+      const uint32_t ctz = min(ffbl32(cl), ffbl32(ch) | 32u);
+      const uint32_t clz = min(ffbh32(ah | bh), ffbh32(al | bl) | 32u);
       const int kk = lane - 2;
       const int lo = max((int)ctz, pm + kk);
       const int hi = min(64 - (int)clz, mrel);
@@ -1290,26 +1307,22 @@ __device__ __forceinline__ int fast_interior_multi(Ext& e, int (&A)[C],
       // antidiagonals in lanes k + 1 (a) and k (b)
       auto range = [&](uint32_t l0, uint32_t h0, uint32_t l1, uint32_t h1,
                        int& L, int& U) {
-        const uint32_t c0 = min((uint32_t)__builtin_ctzg(l0, -1),
-                                (uint32_t)__builtin_ctzg(h0, -1) | 32u);
-        const uint32_t c1 = min((uint32_t)__builtin_ctzg(l1, -1),
-                                (uint32_t)__builtin_ctzg(h1, -1) | 32u);
-        const uint32_t z0 = min((uint32_t)__builtin_clzg(h0, -1),
-                                (uint32_t)__builtin_clzg(l0, -1) | 32u);
-        const uint32_t z1 = min((uint32_t)__builtin_clzg(h1, -1),
-                                (uint32_t)__builtin_clzg(l1, -1) | 32u);
+        const uint32_t c0 = min(ffbl32(l0), ffbl32(h0) | 32u);
+        const uint32_t c1 = min(ffbl32(l1), ffbl32(h1) | 32u);
+        const uint32_t z0 = min(ffbh32(h0), ffbh32(l0) | 32u);
+        const uint32_t z1 = min(ffbh32(h1), ffbh32(l1) | 32u);
         // (an empty mask gives c = z = 2^32 - 1: L above, U below any cell)
         L = (int)min(min(c0, 64u) * 2, min(c1, 64u) * 2 + 1);
         U = max(c0 >= 64u ? -1 : (int)(63 - z0) * 2,
                 c1 >= 64u ? -1 : (int)(63 - z1) * 2 + 1);
       };
       int La, Ua, Lb, Ub;
-      range((uint32_t)wave_shr1(ml0, 0), (uint32_t)wave_shr1(mh0, 0),
-            (uint32_t)wave_shr1(ml1, 0), (uint32_t)wave_shr1(mh1, 0), La, Ua);
-      range((uint32_t)wave_shr1(wave_shr1(ml0, 0), 0),
-            (uint32_t)wave_shr1(wave_shr1(mh0, 0), 0),
-            (uint32_t)wave_shr1(wave_shr1(ml1, 0), 0),
-            (uint32_t)wave_shr1(wave_shr1(mh1, 0), 0), Lb, Ub);
+      range((uint32_t)wave_shr1_z(ml0), (uint32_t)wave_shr1_z(mh0),
+            (uint32_t)wave_shr1_z(ml1), (uint32_t)wave_shr1_z(mh1), La, Ua);
+      range((uint32_t)wave_shr1_z(wave_shr1_z(ml0)),
+            (uint32_t)wave_shr1_z(wave_shr1_z(mh0)),
+            (uint32_t)wave_shr1_z(wave_shr1_z(ml1)),
+            (uint32_t)wave_shr1_z(wave_shr1_z(mh1)), Lb, Ub);
       const int kk = lane - 2;
       const int lo = max(min(La, Lb + 1), pm + kk);
       const int hi = min(max(Ua, Ub) + 1, mrel);

@@ -7,7 +7,8 @@ of a wave meeting at every cross-lane operation; see emu_runtime.cpp) into
 Textual changes make the kernel source host C++: the GPU intrinsic
 name bound to the write-lane declaration is dropped (the runtime defines the
 function), the register-class letters of the empty optimisation-barrier asm
-statements become the host's general class, and the occupancy hint on kernel
+statements become the host's general class, the two bit-scan instructions
+written as asm statements become calls of host functions of the runtime, and the occupancy hint on kernel
 definitions (a register budget for the GPU compiler) is dropped; a trace
 hook after the wave kernel's tier loop reports the tier each extension ends
 on to the runtime, and every shared-memory declaration registers its
@@ -33,6 +34,9 @@ CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 def host_source(text: str) -> str:
     text = re.sub(r'__asm\(\s*"llvm\.amdgcn\.writelane\.i32"\s*\)', "", text)
     text = re.sub(r'"\+[sv]"', '"+r"', text)
+    # the bit scans written as single instructions become host functions
+    text = re.sub(r'asm\("v_ffb([lh])_(?:b32|u32) %0, %1" : "=v"\((\w+)\) : "v"\((\w+)\)\);',
+                  r'\2 = emu_ffb\1_32(\3);', text)
     text = re.sub(r'__attribute__\(\(amdgpu_waves_per_eu\([^()]*\)\)\)', "", text)
     # shared variables start with garbage in every block
     def _shared(m):

@@ -131,6 +131,10 @@ inline uint32_t emu_perm(uint32_t s0, uint32_t s1, uint32_t sel) {
   }
   return r;
 }
+// v_ffbl_b32 / v_ffbh_u32: lowest / highest set bit (counted from the
+// top for ffbh), 0xffffffff for 0
+inline uint32_t emu_ffbl_32(uint32_t x) { return x ? (uint32_t)__builtin_ctz(x) : 0xffffffffu; }
+inline uint32_t emu_ffbh_32(uint32_t x) { return x ? (uint32_t)__builtin_clz(x) : 0xffffffffu; }
 #define __builtin_amdgcn_alignbit(hi, lo, sh) emu_alignbit((hi), (lo), (sh))
 #define __builtin_amdgcn_perm(s0, s1, sel) emu_perm((s0), (s1), (sel))
 #define __builtin_amdgcn_ubfe(v, o, w) emu_ubfe((v), (o), (w))
