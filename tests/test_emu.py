@@ -26,6 +26,27 @@ def emu():
     e.close()
 
 
+def test_host_translation_leaves_no_device_instruction():
+    """The CPU build's source translation maps every instruction the kernel
+    source writes as an asm statement (the bit scans) to a host function;
+    only the empty register barriers stay asm, with the host's register
+    class.  A new device instruction without a mapping fails here, not in
+    the host assembler."""
+    import re
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "emu"))
+    import build as emu_build
+    src = os.path.join(emu_build.CSRC, "xdrop_kernels.hip")
+    with open(src, encoding="utf-8") as f:
+        text = f.read()
+    assert re.search(r'asm\("v_ffb', text)  # the scans are written out
+    host = emu_build.host_source(text)
+    code = "\n".join(ln.split("//")[0] for ln in host.splitlines())
+    for m in re.finditer(r'\basm\s*(?:volatile\s*)?\(\s*"([^"]*)"', code):
+        assert m.group(1) == "", m.group(0)
+    assert "emu_ffbl_32(" in host and "emu_ffbh_32(" in host
+
+
 def _enc(s):
     return np.array([DNA[c] for c in s], dtype=np.uint8)
 
