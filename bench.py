@@ -309,6 +309,54 @@ def other_workload(xdrop, ctx, name, steps, stream):
             "seeds": n, "X": scheme.X}
 
 
+def block_tier_probe(args):
+    """The block tier alone: unrelated random pairs of equal length with no
+    X-drop (X = 2^31 - 1), so every extension runs all m + n antidiagonals
+    and its band grows to the full matrix width; the WORKGROUP form puts
+    every extension on the block tier from the first antidiagonal.  Per-phase
+    HIP events on the launch stream; ns per antidiagonal of one extension =
+    the tier's time / (m + n)."""
+    import numpy as np
+    import torch
+    from paper_2304_08662_amd import inputs, xdrop
+    ctx = xdrop.Context(0)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    shapes = [(1, 1000, 4), (1, 2000, 4), (256, 1000, 4), (1024, 1000, 4),
+              (256, 1000, 20)]
+    for npairs, length, alpha in shapes:
+        rng = np.random.default_rng(5)
+        pairs = [(rng.integers(0, alpha, length).astype(np.uint8),
+                  rng.integers(0, alpha, length).astype(np.uint8), 0, 0, 0)
+                 for _ in range(npairs)]
+        batch = inputs._assemble(pairs, alpha, {})
+        if alpha == 4:
+            scheme = inputs.Scheme(4, 1, -1, -1, 2**31 - 1)
+        else:
+            scheme = inputs.Scheme(
+                20, gap=-2, X=2**31 - 1,
+                matrix=inputs.stand_in_substitution_matrix())
+        sc = scoring_for(xdrop, scheme)
+        packed = batch.packed() if alpha == 4 else batch.codes
+        dev = xdrop.to_device(packed, batch.offsets, batch.seeds)
+        res = xdrop.result_buffer(len(batch.seeds))
+        opts = xdrop.options(xdrop.VARIANT_WORKGROUP)
+        for _ in range(args.warmup):
+            ctx.extend_batch(*dev, sc, res, opts, stream=stream)
+        stream.synchronize()
+        # (phases: prep, wave kernel, handed-on extensions, block tier and
+        # device-memory tier, combine)
+        ph = phase_times(ctx, dev, sc, res, opts, stream, args.steps)
+        steps = 2 * length  # antidiagonals of one extension (m + n)
+        print(json.dumps({
+            "block_tier": {"pairs": npairs, "length": length,
+                           "alphabet": alpha,
+                           "workgroup_ms": round(float(ph[3]), 4),
+                           "ns_per_antidiagonal":
+                               round(float(ph[3]) * 1e6 / steps, 1),
+                           "tiers": ctx.last_stats()}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +380,10 @@ def main():
                          "if it exists, else written by the tuning run")
     ap.add_argument("--others", default="dna-1k,dna-tail",
                     help="other workloads timed after the headline one")
+    ap.add_argument("--block-tier", action="store_true",
+                    help="only time the block tier (bands of 513-2,048 "
+                         "cells) on unrelated random pairs with no X-drop "
+                         "and exit: one JSON line per batch shape")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB five "
                          "times (reference for HBM byte counters) and exit")
@@ -357,6 +409,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written":
                           nbytes, "copies": 5}), flush=True)
+        return
+    if args.block_tier:
+        block_tier_probe(args)
         return
     log(f"generating {args.workload} x{args.scale}")
     batch, scheme = load_workload(args.workload, args.scale)
